@@ -1,0 +1,220 @@
+"""FP64 render, backward and loss of the SVLF per-ray path.
+
+Follows SVLF section 4 with the single-decoder reading used by the library:
+
+* per hit (leaf, t_in, t_out): the sample point is the segment midpoint
+  t_mid = (t_in + t_out) / 2, p = o + t_mid d (the paper samples its colour
+  features at a point inside the voxel between x1 and x2, section 4.2);
+* x = psi(p; Z): trilinear interpolation of the leaf's 8 corner embeddings
+  (section 4.1), u = clamp((p - lo) / h, 0, 1), w_j = prod_a (u_a or 1 - u_a);
+* one ReLU MLP (section 4.5 "Architecture") maps x to 4 outputs o; the colour
+  is sigmoid(o_0..2), the density sigma = ReLU(o_3);
+* optical thickness (section 4 footnote: integral of density along the
+  segment) tau = sigma * (t_out - t_in) / h ("voxel" mode: density in units of
+  voxel edges); "direct" mode tau = sigma, "world" mode tau = sigma * dt;
+* Eq. 3: c(r) = sum_i T_i (1 - e^{-tau_i}) c_i, T_i = prod_{j<i} e^{-tau_j},
+  over the first min(N, K) voxels in order along the ray; depth and the
+  accumulated opacity use the same weights (depth = sum w_i t_mid_i,
+  acc = sum w_i); a ray with no hits gives zeros.
+
+``bf16=True`` rounds (round to nearest even) the features, the weights, the
+MLP input x and every hidden activation after ReLU to bfloat16 before use;
+in the backward it also rounds each layer's incoming gradient before the
+products.  All accumulation stays in FP64.
+
+No GPU code and no automatic differentiation is used; the backward is
+derived by hand from the formulas above.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .octree import Octree
+
+TAU_MODES = ("voxel", "direct", "world")
+
+
+def bf16_round(x):
+    """Round FP64 values to the nearest bfloat16 (8 significant bits, ties
+    to even, bfloat16 exponent range including its subnormals)."""
+    x = np.asarray(x, np.float64)
+    m, e = np.frexp(x)                     # x = m 2^e, 0.5 <= |m| < 1
+    e = np.maximum(e, -125)                # subnormal spacing 2^-133
+    scale = np.ldexp(1.0, 8 - e)
+    return np.rint(x * scale) / scale
+
+
+def split_params(params, widths):
+    """Views W_l (out, in) and b_l (out,) of the flat FP64 parameter vector."""
+    params = np.asarray(params, np.float64)
+    out, off = [], 0
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        W = params[off:off + fo * fi].reshape(fo, fi)
+        off += fo * fi
+        b = params[off:off + fo]
+        off += fo
+        out.append((W, b))
+    if off != params.size:
+        raise ValueError("parameter vector does not match widths")
+    return out
+
+
+def sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def mlp_forward(params, widths, X, bf16=False):
+    """Returns (o, acts, pres): output pre-activations o (n, 4), the inputs
+    of every layer acts[l] and hidden pre-activations pres[l]."""
+    layers = split_params(params, widths)
+    r = bf16_round if bf16 else (lambda v: v)
+    a = r(np.asarray(X, np.float64))
+    acts, pres = [], []
+    for li, (W, b) in enumerate(layers):
+        acts.append(a)
+        z = a @ r(W).T + b
+        if li < len(layers) - 1:
+            pres.append(z)
+            a = r(np.maximum(z, 0.0))
+        else:
+            return z, acts, pres
+    raise ValueError("empty MLP")
+
+
+def interpolation_weights(u):
+    """w (n, 8): corner j weight = prod over axes of u_a if bit a of j else
+    1 - u_a (textbook trilinear weights)."""
+    w = np.ones((u.shape[0], 8))
+    for j in range(8):
+        for a in range(3):
+            w[:, j] *= u[:, a] if (j >> a) & 1 else 1.0 - u[:, a]
+    return w
+
+
+class RenderState:
+    """Everything the backward needs (dense [n_rays, K] layout)."""
+
+
+def render(octree: Octree, features, params, widths, o, d, hits, tau_mode="voxel",
+           bf16=False):
+    """Forward render.  ``hits`` = (hit_leaf, hit_tin, hit_tout, hit_count)
+    from ``trace.trace_hits``.  Returns (rgb (n,3), depth (n,), acc (n,),
+    state)."""
+    if tau_mode not in TAU_MODES:
+        raise ValueError(tau_mode)
+    hit_leaf, hit_tin, hit_tout, _ = hits
+    n, K = hit_leaf.shape
+    o = np.asarray(o, np.float64)
+    d = np.asarray(d, np.float64)
+    F = np.asarray(features, np.float64)
+    if bf16:
+        F = bf16_round(F)
+    valid = hit_leaf >= 0
+    ray_i, slot_i = np.nonzero(valid)
+    leaf = hit_leaf[ray_i, slot_i].astype(np.int64)
+    t0 = hit_tin[ray_i, slot_i].astype(np.float64)
+    t1 = hit_tout[ray_i, slot_i].astype(np.float64)
+    L = octree.depth
+    h = 2.0 / (1 << L)
+    tm = 0.5 * (t0 + t1)
+    p = o[ray_i] + tm[:, None] * d[ray_i]
+    lo = -1.0 + octree.leaf_ijk[leaf].astype(np.float64) * h
+    u = np.clip((p - lo) / h, 0.0, 1.0)
+    wj = interpolation_weights(u)
+    corners = octree.leaf_corners[leaf]                 # (m, 8)
+    X = np.einsum("mj,mjc->mc", wj, F[corners])
+    out, acts, pres = mlp_forward(params, widths, X, bf16)
+    c = sigmoid(out[:, :3])
+    sigma = np.maximum(out[:, 3], 0.0)
+    dt = t1 - t0
+    dtau = {"voxel": dt / h, "direct": np.ones_like(dt), "world": dt}[tau_mode]
+    tau_h = sigma * dtau
+    # dense per-ray layout, zero padded
+    tau = np.zeros((n, K))
+    col = np.zeros((n, K, 3))
+    tmid = np.zeros((n, K))
+    tau[ray_i, slot_i] = tau_h
+    col[ray_i, slot_i] = c
+    tmid[ray_i, slot_i] = tm
+    # Eq. 3
+    T = np.exp(-(np.cumsum(tau, axis=1) - tau))
+    alpha = -np.expm1(-tau)
+    w = T * alpha
+    rgb = np.sum(w[:, :, None] * col, axis=1)
+    depth = np.sum(w * tmid, axis=1)
+    acc = np.sum(w, axis=1)
+    st = RenderState()
+    st.__dict__.update(dict(octree=octree, widths=tuple(widths), params=np.asarray(params, np.float64),
+                            bf16=bf16, n=n, K=K, ray_i=ray_i, slot_i=slot_i, wj=wj,
+                            corners=corners, X=X, out=out, acts=acts, pres=pres, c=c,
+                            sigma=sigma, dtau=dtau, tau=tau, col=col, tmid=tmid, T=T,
+                            w=w, rgb=rgb, depth=depth, acc=acc, n_vertices=F.shape[0],
+                            C=F.shape[1]))
+    return rgb, depth, acc, st
+
+
+def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
+    """Hand-derived backward of ``render`` for upstream gradients of rgb,
+    depth and acc.  Returns (grad_features (n_vertices, C), grad_params)."""
+    n, K = st.n, st.K
+    g_rgb = np.asarray(grad_rgb, np.float64).reshape(n, 3)
+    g_d = np.asarray(grad_depth, np.float64).reshape(n)
+    g_a = np.zeros(n) if grad_acc is None else np.asarray(grad_acc, np.float64).reshape(n)
+    T, w, tau, col, tmid = st.T, st.w, st.tau, st.col, st.tmid
+    T_next = T * np.exp(-tau)
+    # suffix sums S_i = sum_{j > i} w_j x_j
+    wc = w[:, :, None] * col
+    S_c = np.sum(wc, axis=1, keepdims=True) - np.cumsum(wc, axis=1)
+    wt = w * tmid
+    S_t = np.sum(wt, axis=1, keepdims=True) - np.cumsum(wt, axis=1)
+    S_a = np.sum(w, axis=1, keepdims=True) - np.cumsum(w, axis=1)
+    g_tau = (np.sum(g_rgb[:, None, :] * (T_next[:, :, None] * col - S_c), axis=2)
+             + g_d[:, None] * (T_next * tmid - S_t)
+             + g_a[:, None] * (T_next - S_a))
+    g_col = w[:, :, None] * g_rgb[:, None, :]
+    ri, si = st.ray_i, st.slot_i
+    g_sigma = g_tau[ri, si] * st.dtau
+    g_out = np.zeros_like(st.out)
+    g_out[:, 3] = np.where(st.out[:, 3] > 0.0, g_sigma, 0.0)
+    c = st.c
+    g_out[:, :3] = g_col[ri, si] * c * (1.0 - c)
+    # MLP backward
+    layers = split_params(st.params, st.widths)
+    r = bf16_round if st.bf16 else (lambda v: v)
+    grads = []
+    g_z = g_out
+    for li in range(len(layers) - 1, -1, -1):
+        W, b = layers[li]
+        a = st.acts[li]
+        g_zr = r(g_z)
+        grads.append((g_zr.T @ a, np.sum(g_z, axis=0)))
+        g_a = g_zr @ r(W)
+        if li > 0:
+            g_z = np.where(st.pres[li - 1] > 0.0, g_a, 0.0)
+        else:
+            g_X = g_a
+    grads.reverse()
+    grad_params = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    grad_F = np.zeros((st.n_vertices, st.C))
+    contrib = st.wj[:, :, None] * g_X[:, None, :]       # (m, 8, C)
+    np.add.at(grad_F, st.corners.ravel(), contrib.reshape(-1, st.C))
+    return grad_F, grad_params
+
+
+def loss(rgb, depth, rgb_t, depth_t, lam_depth=0.1):
+    """L = mean over rays and channels of (rgb - rgb*)^2
+         + lam * mean over rays of |depth - depth*|; returns (L, dL/drgb,
+    dL/ddepth) with sign(0) = 0."""
+    rgb = np.asarray(rgb, np.float64)
+    depth = np.asarray(depth, np.float64)
+    n = rgb.shape[0]
+    dr = rgb - np.asarray(rgb_t, np.float64)
+    dd = depth - np.asarray(depth_t, np.float64)
+    L = np.sum(dr * dr) / (3.0 * n) + lam_depth * np.sum(np.abs(dd)) / n
+    return L, 2.0 * dr / (3.0 * n), lam_depth * np.sign(dd) / n
+
+
+def psnr(img, ref, peak=1.0):
+    mse = np.mean((np.asarray(img, np.float64) - np.asarray(ref, np.float64)) ** 2)
+    return float("inf") if mse == 0 else 10.0 * np.log10(peak * peak / mse)

@@ -1,0 +1,335 @@
+"""Pins for the oracle's render, backward and loss (SVLF sections 4.1-4.3,
+Eq. 3, section 4 footnote on optical thickness).
+
+* trilinear interpolation: corners, centre, partition of unity, continuity
+  across a shared face;
+* MLP special cases with hand-computed outputs;
+* closed-form single-voxel renders, telescoping with a constant decoder,
+  empty scenes, compositing invariants;
+* central finite differences of the loss for features and weights, and the
+  conservation identity sum(grad_features) = sum over hits of dL/dx;
+* the bfloat16 rounding against torch's float32 -> bfloat16 conversion.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.octree import Octree
+from oracle.render import (bf16_round, interpolation_weights, loss, mlp_forward,
+                           render, render_backward, split_params)
+from oracle.trace import trace_hits
+from synth.configs import param_count, tiny_workload, xavier_params
+from tests.helpers import crafted_occupancy, random_rays
+
+
+def _zero_mlp(widths, out_bias):
+    p = np.zeros(param_count(widths))
+    p[-4:] = out_bias
+    return p
+
+
+# ------------------------------------------------------------ interpolation
+
+def test_trilinear_weights_corners_centre_unity():
+    rng = np.random.default_rng(0)
+    u = rng.uniform(0, 1, (50, 3))
+    w = interpolation_weights(u)
+    np.testing.assert_allclose(w.sum(axis=1), 1.0, rtol=0, atol=1e-15)
+    assert np.all(w >= 0)
+    for j in range(8):
+        corner = np.array([[j & 1, (j >> 1) & 1, (j >> 2) & 1]], np.float64)
+        e = np.zeros(8)
+        e[j] = 1.0
+        np.testing.assert_array_equal(interpolation_weights(corner)[0], e)
+    np.testing.assert_array_equal(interpolation_weights(np.full((1, 3), 0.5))[0], np.full(8, 0.125))
+
+
+def _render_one(oc, F, params, widths, o, d, K=4, **kw):
+    hits = trace_hits(oc, o, d, K)
+    return hits, render(oc, F, params, widths, o, d, hits, **kw)
+
+
+def test_interpolation_at_corner_centre_and_shared_face():
+    """Identity-like decoder exposes x: with W1 = I (C=4 -> 4 hidden) and a
+    linear read-out of hidden unit 0 into o_3, sigma = relu(x_0)."""
+    depth = 1
+    oc = Octree([[0, 0, 0], [1, 0, 0]], depth)   # two leaves sharing face x=0
+    C = 4
+    widths = (C, 4, 4)
+    p = np.zeros(param_count(widths))
+    W = split_params(p, widths)
+    W[0][0][:] = np.eye(4)
+    W[1][0][3, 0] = 1.0
+    rng = np.random.default_rng(2)
+    F = rng.uniform(0.1, 1.0, (oc.n_vertices, C))
+    # a ray along +x at y, z chosen so that the midpoint of each leaf
+    # segment is at u = (0.5, uy, uz); compare x with direct weights
+    uy, uz = 0.25, 0.75
+    o = np.array([[-2.0, -1.0 + uy, -1.0 + uz]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0]], np.float32)
+    hits, (rgb, depth_, acc, st) = _render_one(oc, F, p, widths, o, d)
+    assert st.X.shape[0] == 2
+    for hidx in range(2):
+        leaf = hits[0][0, hidx]
+        w = interpolation_weights(np.array([[0.5, uy, uz]]))[0]
+        np.testing.assert_allclose(st.X[hidx], w @ F[oc.leaf_corners[leaf]], rtol=1e-14)
+    # continuity: a point on the shared face (x = 0) interpolates the same
+    # from both leaves: u_x = 1 in leaf 0 and u_x = 0 in leaf 1
+    w0 = interpolation_weights(np.array([[1.0, uy, uz]]))[0]
+    w1 = interpolation_weights(np.array([[0.0, uy, uz]]))[0]
+    x0 = w0 @ F[oc.leaf_corners[0]]
+    x1 = w1 @ F[oc.leaf_corners[1]]
+    np.testing.assert_allclose(x0, x1, rtol=1e-14)
+
+
+# ------------------------------------------------------------ MLP
+
+def test_mlp_zero_weights_constant_output():
+    widths = (8, 16, 16, 4)
+    p = _zero_mlp(widths, [0.3, -1.0, 2.0, 0.7])
+    X = np.random.default_rng(0).normal(size=(10, 8))
+    out, _, _ = mlp_forward(p, widths, X)
+    np.testing.assert_array_equal(out, np.tile([0.3, -1.0, 2.0, 0.7], (10, 1)))
+
+
+def test_mlp_hand_computed():
+    # 2 -> 2 -> 4 with W1 = [[1,-1],[2,1]], b1 = [0, -1]; x = (3, 1)
+    # z1 = (2, 6), a1 = (2, 6); W2 rows pick: o = (a0, a1, a0 - a1, -a0) + b2
+    widths = (2, 2, 4)
+    p = np.array([1, -1, 2, 1, 0, -1,
+                  1, 0, 0, 1, 1, -1, -1, 0, 0.5, 0, 0, 0], np.float64)
+    out, acts, pres = mlp_forward(p, widths, np.array([[3.0, 1.0]]))
+    np.testing.assert_array_equal(pres[0], [[2.0, 6.0]])
+    np.testing.assert_array_equal(out, [[2.5, 6.0, -4.0, -2.0]])
+    # negative hidden pre-activation is clamped: x = (-1, 0) -> z1 = (-1, -3)
+    out, _, _ = mlp_forward(p, widths, np.array([[-1.0, 0.0]]))
+    np.testing.assert_array_equal(out, [[0.5, 0.0, 0.0, 0.0]])
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("tau_mode", ["voxel", "direct", "world"])
+def test_single_voxel_closed_form(tau_mode):
+    depth = 2
+    leaf = [1, 2, 1]
+    oc = Octree([leaf], depth)
+    h = 0.5
+    widths = (4, 8, 4)
+    z = np.array([0.2, -0.4, 0.6, 0.1])
+    F = np.tile(z, (oc.n_vertices, 1))          # all corners equal -> x = z
+    rng = np.random.default_rng(4)
+    p = xavier_params(rng, widths).astype(np.float64)
+    p[-4:] = [0.1, -0.2, 0.3, 0.9]               # make sigma > 0
+    out, _, _ = mlp_forward(p, widths, z[None, :])
+    c = 1.0 / (1.0 + np.exp(-out[0, :3]))
+    sigma = max(out[0, 3], 0.0)
+    assert sigma > 0
+    lo = np.array([-1.0 + 1 * h, -1.0 + 2 * h, -1.0 + 1 * h])
+    ctr = lo + h / 2
+    # axis-aligned ray through the centre: dt = h
+    o = np.array([[-3.0, ctr[1], ctr[2]]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0]], np.float32)
+    _, (rgb, dep, acc, _) = _render_one(oc, F, p, widths, o, d, tau_mode=tau_mode)
+    dt = h
+    tau = {"voxel": sigma * dt / h, "direct": sigma, "world": sigma * dt}[tau_mode]
+    a = 1.0 - np.exp(-tau)
+    t_mid = (lo[0] - (-3.0)) + h / 2
+    np.testing.assert_allclose(rgb[0], c * a, rtol=1e-12)
+    np.testing.assert_allclose(acc[0], a, rtol=1e-12)
+    np.testing.assert_allclose(dep[0], a * t_mid, rtol=1e-12)
+    # main diagonal through the cell: dt = h (per unit of the unnormalised
+    # direction (1,1,1)), so the voxel-mode tau is sigma
+    o = (ctr - 2.0).astype(np.float32)[None, :]
+    d = np.array([[1.0, 1.0, 1.0]], np.float32)
+    _, (rgb, dep, acc, _) = _render_one(oc, F, p, widths, o, d, tau_mode=tau_mode)
+    tau = {"voxel": sigma, "direct": sigma, "world": sigma * h}[tau_mode]
+    np.testing.assert_allclose(acc[0], 1.0 - np.exp(-tau), rtol=1e-12)
+
+
+def test_telescoping_constant_decoder():
+    """Constant decoder: acc = 1 - exp(-sigma sum(dt)/h), rgb = c acc."""
+    depth = 3
+    oc = Octree(crafted_occupancy("random30", depth, seed=1), depth)
+    widths = (4, 8, 4)
+    p = _zero_mlp(widths, [0.5, -0.5, 1.0, 0.8])
+    F = np.random.default_rng(1).normal(size=(oc.n_vertices, 4))
+    o, d = random_rays(np.random.default_rng(5), 200)
+    K = 64
+    hits, (rgb, dep, acc, _) = _render_one(oc, F, p, widths, o, d, K=K)
+    h = 2.0 / 8
+    dt = np.where(hits[0] >= 0, hits[2].astype(np.float64) - hits[1], 0.0).sum(axis=1)
+    exp_acc = 1.0 - np.exp(-0.8 * dt / h)
+    np.testing.assert_allclose(acc, exp_acc, rtol=1e-12, atol=1e-15)
+    c = 1.0 / (1.0 + np.exp(-np.array([0.5, -0.5, 1.0])))
+    np.testing.assert_allclose(rgb, exp_acc[:, None] * c[None, :], rtol=1e-12, atol=1e-15)
+
+
+def test_empty_scene_and_missing_rays():
+    widths = (4, 8, 4)
+    p = _zero_mlp(widths, [1, 1, 1, 1])
+    oc = Octree(np.zeros((0, 3)), 2)
+    o, d = random_rays(np.random.default_rng(0), 20)
+    F = np.zeros((0, 4))
+    hits, (rgb, dep, acc, st) = _render_one(oc, F, p, widths, o, d)
+    assert np.all(hits[3] == 0)
+    assert np.all(rgb == 0) and np.all(dep == 0) and np.all(acc == 0)
+    gF, gp = render_backward(st, np.ones((20, 3)), np.ones(20), np.ones(20))
+    assert gF.shape == (0, 4) and np.all(gp == 0)
+
+
+def test_compositing_invariants():
+    w = tiny_workload(3, 4, 8, (8, 16, 16, 4), 6)
+    sc = w.scene()
+    oc = Octree(sc.leaf_ijk, sc.depth)
+    F = w.features().astype(np.float64) * 20.0      # large sigma somewhere
+    p = w.params().astype(np.float64)
+    p[-1] = 2.0
+    o, d = random_rays(np.random.default_rng(9), 300)
+    hits, (rgb, dep, acc, st) = _render_one(oc, F, p, w.widths, o, d, K=6)
+    T = st.T
+    assert np.all((T >= 0) & (T <= 1))
+    assert np.all(np.diff(T, axis=1) <= 1e-15)
+    np.testing.assert_allclose(acc, st.w.sum(axis=1), rtol=1e-14)
+    assert np.all((acc >= 0) & (acc <= 1))
+    assert np.all(rgb >= 0) and np.all(rgb <= acc[:, None] + 1e-15)
+    cnt = hits[3]
+    has = cnt > 0
+    first_in = hits[1][has, 0].astype(np.float64)
+    last_out = hits[2][has, cnt[has] - 1].astype(np.float64)
+    assert np.all(dep[has] >= acc[has] * first_in - 1e-12)
+    assert np.all(dep[has] <= acc[has] * last_out + 1e-12)
+    assert np.all(dep[~has] == 0)
+
+
+# ------------------------------------------------------------ gradients
+
+def _fd_setup(seed, tau_mode="voxel", bf16=False):
+    w = tiny_workload(seed, 3, 8, (8, 16, 16, 4), 4, n_obj=2)
+    sc = w.scene()
+    oc = Octree(sc.leaf_ijk, sc.depth)
+    F = w.features().astype(np.float64)
+    p = w.params().astype(np.float64)
+    p[-1] = 0.5                                   # sigma mostly positive
+    rng = np.random.default_rng(seed)
+    o, d = random_rays(rng, 64, inside_frac=0.1, axis_frac=0.0)
+    hits = trace_hits(oc, o, d, 4)
+    rgb_t = rng.uniform(0, 1, (64, 3))
+    dep_t = rng.uniform(0, 4, 64)
+    return oc, F, p, w.widths, o, d, hits, rgb_t, dep_t
+
+
+def _loss_at(oc, F, p, widths, o, d, hits, rgb_t, dep_t, tau_mode):
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits, tau_mode=tau_mode)
+    return loss(rgb, dep, rgb_t, dep_t)[0], st, rgb, dep
+
+
+def _pattern(st, dep, dep_t):
+    """Which side of every kink the evaluation is on (ReLU inputs, the
+    sigma ReLU and the L1 residual)."""
+    return np.concatenate([np.concatenate([z.ravel() > 0 for z in st.pres]),
+                           st.out[:, 3] > 0, dep - dep_t > 0])
+
+
+@pytest.mark.parametrize("tau_mode", ["voxel", "world"])
+def test_gradients_against_central_differences(tau_mode):
+    oc, F, p, widths, o, d, hits, rgb_t, dep_t = _fd_setup(12, tau_mode)
+    L0, st, rgb, dep = _loss_at(oc, F, p, widths, o, d, hits, rgb_t, dep_t, tau_mode)
+    base = _pattern(st, dep, dep_t)
+    _, g_rgb, g_dep = loss(rgb, dep, rgb_t, dep_t)
+    gF, gp = render_backward(st, g_rgb, g_dep)
+    assert np.count_nonzero(gF) > 0
+
+    def fd_of(Fx_p, Fx_m, px_p, px_m, eps):
+        Lp, stp, _, dp = _loss_at(oc, Fx_p, px_p, widths, o, d, hits, rgb_t, dep_t, tau_mode)
+        Lm, stm, _, dm = _loss_at(oc, Fx_m, px_m, widths, o, d, hits, rgb_t, dep_t, tau_mode)
+        # an evaluation that straddles a kink is not a derivative: skip it
+        if not (np.array_equal(_pattern(stp, dp, dep_t), base)
+                and np.array_equal(_pattern(stm, dm, dep_t), base)):
+            return None
+        return (Lp - Lm) / (2 * eps)
+
+    def floor(eps):
+        return 64 * np.finfo(np.float64).eps * abs(L0) / eps
+
+    rng = np.random.default_rng(0)
+    touched = np.unique(st.corners)
+    checked = skipped = 0
+    for idx in rng.choice(touched.size, min(60, touched.size), replace=False):
+        v = touched[idx]
+        c = rng.integers(0, F.shape[1])
+        eps = 1e-5 * max(1.0, abs(F[v, c]))
+        Fp = F.copy(); Fp[v, c] += eps
+        Fm = F.copy(); Fm[v, c] -= eps
+        fd = fd_of(Fp, Fm, p, p, eps)
+        if fd is None:
+            skipped += 1
+            continue
+        checked += 1
+        # FD of an FP64 loss: relative 1e-6 plus the round-off floor of
+        # the difference quotient (a few ulps of |L| over eps)
+        assert abs(fd - gF[v, c]) <= 1e-6 * abs(fd) + floor(eps), (v, c, fd, gF[v, c])
+    for k in rng.choice(p.size, 80, replace=False):
+        eps = 1e-5 * max(1.0, abs(p[k]))
+        pp = p.copy(); pp[k] += eps
+        pm = p.copy(); pm[k] -= eps
+        fd = fd_of(F, F, pp, pm, eps)
+        if fd is None:
+            skipped += 1
+            continue
+        checked += 1
+        assert abs(fd - gp[k]) <= 1e-6 * abs(fd) + floor(eps), (k, fd, gp[k])
+    assert skipped <= 0.1 * (checked + skipped)
+
+
+def test_acc_gradient_and_conservation():
+    oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
+    rng = np.random.default_rng(1)
+    g_acc = rng.normal(size=acc.shape)
+    gF, gp = render_backward(st, np.zeros_like(rgb), np.zeros_like(dep), g_acc)
+    k = 5
+    eps = 1e-6
+    for v in np.unique(st.corners)[:k]:
+        Fp = F.copy(); Fp[v, 0] += eps
+        Fm = F.copy(); Fm[v, 0] -= eps
+        ap = render(oc, Fp, p, widths, o, d, hits)[2]
+        am = render(oc, Fm, p, widths, o, d, hits)[2]
+        fd = float(g_acc @ (ap - am)) / (2 * eps)
+        assert abs(fd - gF[v, 0]) <= 1e-6 * max(1e-3, abs(fd))
+    # conservation: trilinear weights of each hit sum to 1, so the total
+    # feature gradient equals the total input gradient over hits
+    g_rgb = rng.normal(size=rgb.shape)
+    g_dep = rng.normal(size=dep.shape)
+    gF, _ = render_backward(st, g_rgb, g_dep)
+    # recover sum over hits of dL/dx by a second path: scale all features
+    # by (1 + e) shifts x by e x, so dL/de = sum_hits <dL/dx, x>
+    e = 1e-6
+    Lp = float(np.sum(g_rgb * render(oc, F * (1 + e), p, widths, o, d, hits)[0])
+               + g_dep @ render(oc, F * (1 + e), p, widths, o, d, hits)[1])
+    Lm = float(np.sum(g_rgb * render(oc, F * (1 - e), p, widths, o, d, hits)[0])
+               + g_dep @ render(oc, F * (1 - e), p, widths, o, d, hits)[1])
+    fd = (Lp - Lm) / (2 * e)
+    assert abs(fd - float(np.sum(gF * F))) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_loss_gradient_closed_form():
+    rgb = np.array([[0.5, 0.2, 0.1], [0.0, 1.0, 0.3]])
+    rgb_t = np.array([[0.4, 0.2, 0.3], [0.0, 0.5, 0.3]])
+    dep = np.array([2.0, 1.0])
+    dep_t = np.array([1.5, 1.0])
+    L, gr, gd = loss(rgb, dep, rgb_t, dep_t, 0.1)
+    assert np.isclose(L, (0.01 + 0.04 + 0.25) / 6 + 0.1 * 0.5 / 2, rtol=1e-15)
+    np.testing.assert_allclose(gr, 2 * (rgb - rgb_t) / 6, rtol=1e-15)
+    np.testing.assert_array_equal(gd, [0.05, 0.0])
+
+
+# ------------------------------------------------------------ bfloat16
+
+def test_bf16_round_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=5000) * 10.0 ** rng.integers(-30, 30, 5000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3e-39, -1e-40]])
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(bf16_round(x32.astype(np.float64)), ref.astype(np.float64))
