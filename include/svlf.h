@@ -1,0 +1,279 @@
+/*
+ * svlf.h -- C-ABI of the SVLF per-ray render library (libsvlf.so, gfx950).
+ *
+ * SVLF ("Sparse Voxel Light Field", RTMV paper arxiv 2205.07058, section 4)
+ * renders a pixel by listing the occupied voxels of a sparse octree that its
+ * ray crosses, decoding every crossed voxel once with a small network into an
+ * optical thickness and a colour, and alpha compositing the results in order
+ * along the ray (section 4.3, Eq. 3).  This library implements that per-ray
+ * path with one decoder C -> H ... -> 4 (RGB + sigma) whose input is the
+ * feature interpolated at the middle of the ray's segment in the voxel:
+ *
+ *   svlf_build_octree   sparse octree over occupied leaves (section 4.1)
+ *   svlf_trace_hits     first K leaves crossed by each ray (sections 4.2-4.3)
+ *   svlf_render         traversal + trilinear features + MLP + Eq. 3
+ *   svlf_render_backward  gradients of rgb/depth/acc w.r.t. the features and
+ *                       the MLP parameters (re-traces and recomputes)
+ *   svlf_train_step     render + MSE/L1 loss + backward in one pass
+ *   svlf_adam_step      Adam update of an FP32 parameter vector (section 4.5
+ *                       trains with Adam)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Scene cube [-1,1]^3.  A leaf of an octree of depth L (1 <= L <= 10) is the
+ * cell (i,j,k) of the 2^L grid, lo = -1 + (i,j,k) h, hi = lo + h, h = 2/2^L.
+ * Leaf ids are ranks in ascending Morton order (bit b of i,j,k at bits 3b,
+ * 3b+1, 3b+2).  Vertex ids are ranks of the Morton codes (L+1 bits per axis)
+ * of all corners of occupied leaves; each vertex owns one feature row
+ * (features are shared by adjacent voxels, section 4.1).  Corner j of a leaf
+ * is the vertex (i + (j&1), j + ((j>>1)&1), k + (j>>2)).
+ *
+ * Hit predicate (the ray-AABB test of section 4.2, fixed here so hit lists
+ * are reproducible bit for bit): binary32 round-to-nearest-even arithmetic,
+ * no FMA contraction, no flush to zero; inv_a = 1/d_a; finite inv_a:
+ * t0 = (lo_a-o_a)*inv_a, t1 = (hi_a-o_a)*inv_a, tn_a = min, tf_a = max;
+ * infinite inv_a: the axis is unconstrained if lo_a <= o_a < hi_a (half-open)
+ * and excludes the cell otherwise; t_in = max(tn) clamped below at +0,
+ * t_out = min(tf); hit iff t_in < t_out.  Rays with a non-finite component
+ * or d = 0 hit nothing.  A ray's hit list is its first K hit leaves in
+ * ascending t_in (no ties can occur).
+ *
+ * Per hit: t_mid = (t_in+t_out)/2, p = o + t_mid d, u = clamp((p-lo)/h,0,1),
+ * x = sum_j w_j(u) F[corner j] (trilinear, section 4.1).  MLP: hidden layers
+ * ReLU; rgb = sigmoid(o_0..2); sigma = ReLU(o_3) (section 4.5).  Optical
+ * thickness (section 4 footnote): tau = sigma*(t_out-t_in)/h (VOXEL mode),
+ * sigma (DIRECT) or sigma*(t_out-t_in) (WORLD).  Eq. 3 over the first
+ * min(N,K) hits: w_i = T_i (1 - e^{-tau_i}), T_i = prod_{j<i} e^{-tau_j};
+ * rgb = sum w_i c_i, depth = sum w_i t_mid_i, acc = sum w_i; zero hits give 0.
+ *
+ * Memory and streams
+ * ------------------
+ * Every pointer documented "device" is device memory of the current HIP
+ * device; "host" pointers are host memory.  All arrays are dense, row-major,
+ * little-endian.  The caller owns every buffer and keeps it alive until the
+ * work queued on `stream` (a hipStream_t, NULL = default stream) completes.
+ * The library keeps no pointer after a call returns and holds no global
+ * state besides the per-thread error string; calls are reentrant across
+ * streams.  Calls are asynchronous with respect to the host unless stated.
+ *
+ * Errors
+ * ------
+ * Every call returns SVLF_OK (0) or a negative svlf_status.  Arguments are
+ * validated on the host before anything is queued; a call that fails
+ * validation writes nothing.  HIP launch failures return SVLF_E_HIP;
+ * faults inside a kernel surface at the caller's next synchronisation.
+ * svlf_last_error() returns a message for the last failing call on the
+ * calling thread.  No C++ exception crosses this interface.
+ */
+#ifndef SVLF_H
+#define SVLF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SVLF_OK = 0,
+  SVLF_E_INVAL = -1,        /* NULL pointer, negative size, malformed input */
+  SVLF_E_RANGE = -2,        /* value outside the supported range            */
+  SVLF_E_WORKSPACE = -3,    /* workspace missing or too small               */
+  SVLF_E_UNSUPPORTED = -4,  /* valid but not implemented (e.g. MLP shape)   */
+  SVLF_E_HIP = -5           /* a HIP runtime call failed                    */
+} svlf_status;
+
+#define SVLF_MAX_DEPTH 10
+#define SVLF_MAX_K 16
+#define SVLF_MAX_SCENES 16
+#define SVLF_MAX_LAYERS 8
+
+/* One internal octree node (levels 0 .. depth-1), 8 bytes.
+ * mask bit c (0..7) is set iff child c = x | y<<1 | z<<2 exists.
+ * child: for a node at level < depth-1, the index in the node array of its
+ * first existing child (children of a node are consecutive, in increasing
+ * child index); for a node at level depth-1, the leaf id of its first leaf.
+ * The node array is in level order: level 0 (the root, index 0), then every
+ * level in ascending Morton order. */
+typedef struct {
+  int32_t child;
+  uint32_t mask;
+} svlf_node;
+
+typedef struct {
+  int32_t depth;
+  int64_t n_leaves;
+  int64_t n_vertices;
+  int64_t n_nodes;                              /* internal nodes            */
+  int64_t level_offset[SVLF_MAX_DEPTH + 1];     /* first node of level l;
+                                                   level_offset[depth] = n_nodes */
+} svlf_octree_sizes;
+
+/* A built octree (device arrays owned by the caller). */
+typedef struct {
+  int32_t depth;
+  int64_t n_leaves;
+  int64_t n_vertices;
+  int64_t n_nodes;
+  const svlf_node* nodes;        /* device [n_nodes]                         */
+  const int32_t* leaf_corners;   /* device [n_leaves][8] vertex ids          */
+} svlf_octree;
+
+/* A scene = octree + per-vertex features (section 4.1: one learnable
+ * embedding per octree vertex). */
+typedef struct {
+  svlf_octree octree;
+  const float* features;         /* device [n_vertices][C] FP32 (masters)     */
+  const uint16_t* features_bf16; /* device [n_vertices][C] bfloat16 bits, RNE
+                                    of `features`; required for BF16 precision,
+                                    may be NULL for FP32                     */
+} svlf_scene;
+
+/* The decoder.  widths[0] = C, widths[n_layers] = 4, hidden layers ReLU.
+ * params: device FP32, per layer W[out][in] row-major then b[out], layers
+ * concatenated (n = sum out*in + out).  Supported shapes: C in {8,16,32},
+ * all hidden widths equal H in {32,64}, 1..4 hidden layers. */
+typedef struct {
+  int32_t n_layers;
+  int32_t widths[SVLF_MAX_LAYERS + 1];
+  const float* params;
+} svlf_mlp;
+
+typedef enum { SVLF_TAU_VOXEL = 0, SVLF_TAU_DIRECT = 1, SVLF_TAU_WORLD = 2 } svlf_tau_mode;
+typedef enum { SVLF_FP32 = 0, SVLF_BF16 = 1 } svlf_precision;
+
+typedef struct {
+  int32_t K;                     /* hit cap per ray, 1..SVLF_MAX_K           */
+  int32_t tau_mode;              /* svlf_tau_mode                            */
+  int32_t precision;             /* svlf_precision: MLP operand type; BF16
+                                    rounds features, weights, the MLP input
+                                    and hidden activations to bfloat16 (RNE)
+                                    with FP32 accumulation; traversal, slabs,
+                                    interpolation weights, compositing and
+                                    gradient accumulation stay FP32          */
+  int32_t reserved;              /* must be 0                                */
+} svlf_render_opts;
+
+/* ---------------------------------------------------------------- octree */
+
+/* Sizes of the octree over `n` occupied leaves (host int32 [n][3], any
+ * order, unique, 0 <= coord < 2^depth).  Host-only, synchronous.
+ * Section 4.1 ("Scene volume"). */
+int svlf_build_octree_sizes(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
+                            svlf_octree_sizes* out);
+
+/* Builds the octree on the host and copies it to the device arrays
+ * nodes_dev (n_nodes entries) and leaf_corners_dev (n_leaves*8 entries), sized
+ * by svlf_build_octree_sizes.  leaf_ijk_sorted_host (nullable, host int32
+ * [n][3]) receives the leaves in leaf-id order.  Synchronous: returns after
+ * the copies on `stream` complete.  Section 4.1. */
+int svlf_build_octree(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
+                      svlf_node* nodes_dev, int32_t* leaf_corners_dev,
+                      int32_t* leaf_ijk_sorted_host, void* stream);
+
+/* Same build, host outputs only: nodes_host (n_nodes entries),
+ * leaf_corners_host (n_leaves*8 entries), leaf_ijk_sorted_host (nullable,
+ * n_leaves*3 entries).  Host-only, synchronous, no HIP call.  Section 4.1. */
+int svlf_build_octree_host(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
+                           svlf_node* nodes_host, int32_t* leaf_corners_host,
+                           int32_t* leaf_ijk_sorted_host);
+
+/* ---------------------------------------------------------------- trace */
+
+/* First K hit leaves of each ray (sections 4.2-4.3).  ray_o, ray_d: device
+ * FP32 [n_rays][3].  Outputs (device): hit_leaf int32 [n_rays][K] (-1 padded),
+ * hit_tin / hit_tout FP32 [n_rays][K] (0 padded), hit_count int32 [n_rays]. */
+int svlf_trace_hits(const svlf_octree* oct, const float* ray_o, const float* ray_d,
+                    int64_t n_rays, int32_t K, int32_t* hit_leaf, float* hit_tin,
+                    float* hit_tout, int32_t* hit_count, void* stream);
+
+/* ---------------------------------------------------------------- render */
+
+/* Workspace bytes needed by svlf_render / svlf_render_backward /
+ * svlf_train_step for n_rays rays (all scenes together) with this MLP and
+ * these options: per-ray hit slots (16 bytes x K), per-ray hit counts and
+ * per-block partial sums of the MLP gradient.  Returns 0 on invalid
+ * arguments (see svlf_last_error).  The workspace is device memory owned by
+ * the caller, needs no initialisation, and may not be shared by calls that
+ * run concurrently. */
+size_t svlf_workspace_bytes(const svlf_mlp* mlp, const svlf_render_opts* opts, int64_t n_rays);
+
+/* Forward render of rays grouped by scene (section 4.3, Eq. 3).  Scenes
+ * 0..n_scenes-1 (1 <= n_scenes <= SVLF_MAX_SCENES) share the MLP and C; the
+ * rays of scene s are rows ray_offsets_host[s] .. ray_offsets_host[s+1]-1 of
+ * ray_o / ray_d (device FP32 [n][3], n = ray_offsets_host[n_scenes]).
+ * Outputs (device FP32): out_rgb [n][3], out_depth [n], out_acc [n] (nullable).
+ * All scenes are rendered by one persistent kernel launch. */
+int svlf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                const svlf_mlp* mlp, const svlf_render_opts* opts,
+                const float* ray_o, const float* ray_d,
+                float* out_rgb, float* out_depth, float* out_acc,
+                void* workspace, size_t ws_bytes, void* stream);
+
+/* Backward of svlf_render for upstream gradients grad_rgb [n][3],
+ * grad_depth [n] and grad_acc [n] (device FP32; grad_acc nullable = 0).
+ * Re-traces every ray and recomputes the forward activations.
+ * ACCUMULATES into grad_features[s] (device FP32 [n_vertices_s][C], one per
+ * scene, with FP32 atomics: order-dependent rounding) and grad_params
+ * (device FP32, layout of svlf_mlp.params, reduced deterministically). */
+int svlf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
+                         const int64_t* ray_offsets_host, const svlf_mlp* mlp,
+                         const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                         const float* grad_rgb, const float* grad_depth, const float* grad_acc,
+                         float* const* grad_features, float* grad_params,
+                         void* workspace, size_t ws_bytes, void* stream);
+
+/* One fused training pass: render, loss
+ *   L = sum over rays of ( |rgb - rgb*|^2 / 3 + lambda_depth |depth - depth*| ) * loss_scale
+ * (loss_scale = 1/n gives the mean MSE over channels + lambda times the mean
+ * L1 of depth; sign(0) = 0), and its backward, as svlf_render_backward with
+ * the loss gradient as upstream gradient.  target_rgb [n][3], target_depth [n]
+ * (device FP32).  out_rgb / out_depth (nullable) receive the render.
+ * loss_out (device FP32 scalar, nullable) is overwritten with L. */
+int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                    const svlf_mlp* mlp, const svlf_render_opts* opts,
+                    const float* ray_o, const float* ray_d,
+                    const float* target_rgb, const float* target_depth,
+                    float lambda_depth, float loss_scale,
+                    float* out_rgb, float* out_depth, float* loss_out,
+                    float* const* grad_features, float* grad_params,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- training utilities */
+
+/* Adam (Kingma & Ba; the optimiser of section 4.5) on n FP32 parameters:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).  All device FP32
+ * [n].  If bf16_out (device uint16 [n], nullable) is given, it receives the
+ * RNE bfloat16 bits of the updated p.  If zero_grad != 0, grad is set to 0
+ * after it is read.  step_t >= 1. */
+int svlf_adam_step(float* param, float* grad, float* m, float* v, int64_t n,
+                   float lr, float beta1, float beta2, float eps, int64_t step_t,
+                   uint16_t* bf16_out, int32_t zero_grad, void* stream);
+
+/* dst[i] = RNE bfloat16 bits of src[i] (device, n elements). */
+int svlf_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);
+
+/* dst[i] = value (device FP32, n elements); a kernel, never a memset node. */
+int svlf_fill(float* dst, float value, int64_t n, void* stream);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+/* Evaluates the decoder alone on X (device FP32 [n][C]) with the precision
+ * of opts, writing the 4 raw outputs (before sigmoid/ReLU) to out (device
+ * FP32 [n][4]).  Exposes the MLP of the render kernels for testing. */
+int svlf_mlp_forward(const svlf_mlp* mlp, const svlf_render_opts* opts, const float* X,
+                     int64_t n, float* out, void* stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* svlf_last_error(void);
+
+/* Library version string. */
+const char* svlf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVLF_H */

@@ -1,0 +1,421 @@
+// C-ABI entry points of libsvlf: argument validation, error reporting and
+// launch set-up.  All device work is queued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "svlf_internal.hpp"
+
+namespace svlf {
+namespace {
+thread_local std::string g_error;
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+const char* error_cstr() { return g_error.c_str(); }
+
+}  // namespace svlf
+
+using namespace svlf;
+
+namespace {
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(SVLF_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+std::string who_str(const char* who, const char* what) { return std::string(who) + ": " + what; }
+
+int check_octree(const svlf_octree* oct, const char* who) {
+  if (oct == nullptr) return fail(SVLF_E_INVAL, who_str(who, "octree is NULL"));
+  if (oct->depth < 1 || oct->depth > SVLF_MAX_DEPTH)
+    return fail(SVLF_E_RANGE, who_str(who, "octree depth must be in [1, 10]"));
+  if (oct->n_leaves < 0 || oct->n_nodes < 0 || oct->n_vertices < 0)
+    return fail(SVLF_E_INVAL, who_str(who, "negative octree size"));
+  if (oct->n_leaves > 0 &&
+      (oct->nodes == nullptr || oct->leaf_corners == nullptr || oct->n_nodes < 1))
+    return fail(SVLF_E_INVAL, who_str(who, "octree arrays are NULL"));
+  return SVLF_OK;
+}
+
+struct MlpShape {
+  int C, H, n_hidden;
+  int64_t n_params;
+};
+
+int check_mlp(const svlf_mlp* mlp, MlpShape* sh, const char* who) {
+  if (mlp == nullptr || mlp->params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "mlp or mlp->params is NULL"));
+  const int L = mlp->n_layers;
+  if (L < 2 || L > SVLF_MAX_LAYERS)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "n_layers must be in [2, 5]"));
+  int64_t np = 0;
+  for (int l = 0; l < L; ++l) {
+    if (mlp->widths[l] < 1 || mlp->widths[l + 1] < 1)
+      return fail(SVLF_E_INVAL, who_str(who, "non-positive layer width"));
+    np += static_cast<int64_t>(mlp->widths[l]) * mlp->widths[l + 1] + mlp->widths[l + 1];
+  }
+  const int c = mlp->widths[0], h = mlp->widths[1];
+  if (mlp->widths[L] != 4)
+    return fail(SVLF_E_INVAL, who_str(who, "the last layer must have 4 outputs (RGB, sigma)"));
+  if (c != 8 && c != 16 && c != 32)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "C must be 8, 16 or 32"));
+  if (h != 32 && h != 64)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "hidden width must be 32 or 64"));
+  for (int l = 1; l < L; ++l)
+    if (mlp->widths[l] != h)
+      return fail(SVLF_E_UNSUPPORTED, who_str(who, "hidden layers must have equal widths"));
+  if (L - 1 > 4) return fail(SVLF_E_UNSUPPORTED, who_str(who, "at most 4 hidden layers"));
+  sh->C = c;
+  sh->H = h;
+  sh->n_hidden = L - 1;
+  sh->n_params = np;
+  return SVLF_OK;
+}
+
+int check_opts(const svlf_render_opts* opts, const char* who) {
+  if (opts == nullptr) return fail(SVLF_E_INVAL, who_str(who, "opts is NULL"));
+  if (opts->K < 1 || opts->K > SVLF_MAX_K)
+    return fail(SVLF_E_RANGE, who_str(who, "K must be in [1, 16]"));
+  if (opts->tau_mode < 0 || opts->tau_mode > 2)
+    return fail(SVLF_E_RANGE, who_str(who, "unknown tau_mode"));
+  if (opts->precision != SVLF_FP32 && opts->precision != SVLF_BF16)
+    return fail(SVLF_E_RANGE, who_str(who, "unknown precision"));
+  if (opts->reserved != 0) return fail(SVLF_E_INVAL, who_str(who, "reserved must be 0"));
+  return SVLF_OK;
+}
+
+// Validates the scene list and builds the kernels' scene table.
+int make_table(const svlf_scene* scenes, int n_scenes, const int64_t* offs, bool bf16,
+               float* const* grads, bool need_grads, SceneTable* tab, const char* who) {
+  if (scenes == nullptr) return fail(SVLF_E_INVAL, who_str(who, "scenes is NULL"));
+  if (n_scenes < 1 || n_scenes > SVLF_MAX_SCENES)
+    return fail(SVLF_E_RANGE, who_str(who, "n_scenes must be in [1, 16]"));
+  if (offs == nullptr) return fail(SVLF_E_INVAL, who_str(who, "ray_offsets is NULL"));
+  if (offs[0] != 0) return fail(SVLF_E_INVAL, who_str(who, "ray_offsets[0] must be 0"));
+  if (need_grads && grads == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "grad_features is NULL"));
+  std::memset(tab, 0, sizeof(*tab));
+  tab->n = n_scenes;
+  int64_t blocks = 0;
+  for (int s = 0; s < n_scenes; ++s) {
+    const svlf_scene& sc = scenes[s];
+    int rc = check_octree(&sc.octree, who);
+    if (rc) return rc;
+    if (offs[s + 1] < offs[s])
+      return fail(SVLF_E_INVAL, who_str(who, "ray_offsets must be non-decreasing"));
+    const bool empty = sc.octree.n_leaves == 0;
+    if (!empty) {
+      if (sc.features == nullptr) return fail(SVLF_E_INVAL, who_str(who, "features is NULL"));
+      if (bf16 && sc.features_bf16 == nullptr)
+        return fail(SVLF_E_INVAL, who_str(who, "BF16 precision needs features_bf16"));
+      if (need_grads && grads[s] == nullptr)
+        return fail(SVLF_E_INVAL, who_str(who, "grad_features[s] is NULL"));
+    }
+    DevScene& d = tab->s[s];
+    d.nodes = empty ? nullptr : sc.octree.nodes;
+    d.leaf_corners = sc.octree.leaf_corners;
+    d.feat32 = sc.features;
+    d.feat16 = sc.features_bf16;
+    d.grad = need_grads ? grads[s] : nullptr;
+    d.ray_begin = offs[s];
+    d.ray_end = offs[s + 1];
+    d.depth = sc.octree.depth;
+    d.block_begin = static_cast<int32_t>(blocks);
+    blocks += (offs[s + 1] - offs[s] + kRaysPerBlock - 1) / kRaysPerBlock;
+  }
+  if (blocks > (int64_t(1) << 30))
+    return fail(SVLF_E_RANGE, who_str(who, "too many rays"));
+  tab->n_blocks = static_cast<int32_t>(blocks);
+  return SVLF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace: [hit slots n*K][counts n][per-block dW partials][per-block loss]
+struct WsLayout {
+  size_t hits, cnt, partials, loss, total;
+};
+
+WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
+  WsLayout w;
+  size_t off = 0;
+  w.hits = off;
+  off = align256(off + static_cast<size_t>(n_rays) * K * sizeof(HitRec));
+  w.cnt = off;
+  off = align256(off + static_cast<size_t>(n_rays) * sizeof(int32_t));
+  w.partials = off;
+  off = align256(off + static_cast<size_t>(shade_grid_limit()) * n_params * sizeof(float));
+  w.loss = off;
+  off = align256(off + static_cast<size_t>(shade_grid_limit()) * sizeof(float));
+  w.total = off;
+  return w;
+}
+
+// Shared body of render / render_backward / train_step.
+int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_t* offs,
+              const svlf_mlp* mlp, const svlf_render_opts* opts, const float* ray_o,
+              const float* ray_d, ShadeArgs a, float* const* grad_features, void* ws,
+              size_t ws_bytes, void* stream, const char* who) {
+  int rc = check_opts(opts, who);
+  if (rc) return rc;
+  MlpShape sh;
+  rc = check_mlp(mlp, &sh, who);
+  if (rc) return rc;
+  const bool need_grads = mode != kForward;
+  rc = make_table(scenes, n_scenes, offs, opts->precision == SVLF_BF16, grad_features, need_grads,
+                  &a.tab, who);
+  if (rc) return rc;
+  const int64_t n = offs[n_scenes];
+  if (n > 0 && (ray_o == nullptr || ray_d == nullptr))
+    return fail(SVLF_E_INVAL, who_str(who, "ray_o / ray_d is NULL"));
+  const WsLayout w = ws_layout(n, opts->K, sh.n_params);
+  if (ws == nullptr || ws_bytes < w.total)
+    return fail(SVLF_E_WORKSPACE, who_str(who, "workspace missing or smaller than svlf_workspace_bytes()"));
+  if (n == 0) return SVLF_OK;
+  char* base = static_cast<char*>(ws);
+  a.o = ray_o;
+  a.d = ray_d;
+  a.hits = reinterpret_cast<HitRec*>(base + w.hits);
+  a.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
+  a.ws_partials = reinterpret_cast<float*>(base + w.partials);
+  a.ws_loss = reinterpret_cast<float*>(base + w.loss);
+  a.K = opts->K;
+  a.tau_mode = opts->tau_mode;
+  a.precision = opts->precision;
+  a.C = sh.C;
+  a.H = sh.H;
+  a.n_hidden = sh.n_hidden;
+  a.params = mlp->params;
+  a.n_params = sh.n_params;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_trace_internal(a.tab, ray_o, ray_d, opts->K, const_cast<HitRec*>(a.hits),
+                                       const_cast<int32_t*>(a.cnt), s);
+  if (e != hipSuccess) return hip_fail(e, who);
+  int grid = 0;
+  e = launch_shade(a, mode, s, &grid);
+  if (e == hipErrorNotSupported)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "no kernel for this MLP shape / precision"));
+  if (e != hipSuccess) return hip_fail(e, who);
+  if (mode != kForward) {
+    e = launch_reduce_partials(a.ws_partials, grid, sh.n_params, a.grad_params, a.ws_loss,
+                               mode == kTrain ? a.loss_out : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+  }
+  return SVLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* svlf_last_error(void) { return svlf::error_cstr(); }
+
+const char* svlf_version(void) { return "svlf-mi355x 0.1 (gfx950)"; }
+
+int svlf_build_octree_sizes(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
+                            svlf_octree_sizes* out) {
+  if (out == nullptr) return fail(SVLF_E_INVAL, "svlf_build_octree_sizes: out is NULL");
+  HostOctree h;
+  int rc = build_octree_host(leaf_ijk_host, n, depth, &h, false);
+  if (rc) return rc;
+  *out = h.sizes;
+  return SVLF_OK;
+}
+
+int svlf_build_octree(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
+                      svlf_node* nodes_dev, int32_t* leaf_corners_dev,
+                      int32_t* leaf_ijk_sorted_host, void* stream) {
+  HostOctree h;
+  int rc = build_octree_host(leaf_ijk_host, n, depth, &h, true);
+  if (rc) return rc;
+  if (n > 0 && (nodes_dev == nullptr || leaf_corners_dev == nullptr))
+    return fail(SVLF_E_INVAL, "svlf_build_octree: device arrays are NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n > 0) {
+    hipError_t e = hipMemcpyAsync(nodes_dev, h.nodes.data(), h.nodes.size() * sizeof(svlf_node),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(leaf_corners_dev, h.leaf_corners.data(),
+                         h.leaf_corners.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "svlf_build_octree");
+  }
+  if (leaf_ijk_sorted_host != nullptr && n > 0)
+    std::memcpy(leaf_ijk_sorted_host, h.leaf_ijk_sorted.data(), h.leaf_ijk_sorted.size() * 4);
+  return SVLF_OK;
+}
+
+int svlf_build_octree_host(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
+                           svlf_node* nodes_host, int32_t* leaf_corners_host,
+                           int32_t* leaf_ijk_sorted_host) {
+  HostOctree h;
+  int rc = build_octree_host(leaf_ijk_host, n, depth, &h, true);
+  if (rc) return rc;
+  if (n > 0 && (nodes_host == nullptr || leaf_corners_host == nullptr))
+    return fail(SVLF_E_INVAL, "svlf_build_octree_host: output arrays are NULL");
+  if (n > 0) {
+    std::memcpy(nodes_host, h.nodes.data(), h.nodes.size() * sizeof(svlf_node));
+    std::memcpy(leaf_corners_host, h.leaf_corners.data(), h.leaf_corners.size() * sizeof(int32_t));
+    if (leaf_ijk_sorted_host != nullptr)
+      std::memcpy(leaf_ijk_sorted_host, h.leaf_ijk_sorted.data(), h.leaf_ijk_sorted.size() * 4);
+  }
+  return SVLF_OK;
+}
+
+int svlf_trace_hits(const svlf_octree* oct, const float* ray_o, const float* ray_d,
+                    int64_t n_rays, int32_t K, int32_t* hit_leaf, float* hit_tin,
+                    float* hit_tout, int32_t* hit_count, void* stream) {
+  const char* who = "svlf_trace_hits";
+  int rc = check_octree(oct, who);
+  if (rc) return rc;
+  if (n_rays < 0) return fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
+  if (K < 1 || K > SVLF_MAX_K) return fail(SVLF_E_RANGE, who_str(who, "K must be in [1, 16]"));
+  if (n_rays > (int64_t(1) << 34)) return fail(SVLF_E_RANGE, who_str(who, "too many rays"));
+  if (n_rays == 0) return SVLF_OK;
+  if (ray_o == nullptr || ray_d == nullptr || hit_leaf == nullptr || hit_tin == nullptr ||
+      hit_tout == nullptr || hit_count == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "NULL array"));
+  hipError_t e = launch_trace_public(*oct, ray_o, ray_d, n_rays, K, hit_leaf, hit_tin, hit_tout,
+                                     hit_count, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, who);
+  return SVLF_OK;
+}
+
+size_t svlf_workspace_bytes(const svlf_mlp* mlp, const svlf_render_opts* opts, int64_t n_rays) {
+  const char* who = "svlf_workspace_bytes";
+  if (check_opts(opts, who)) return 0;
+  MlpShape sh;
+  if (check_mlp(mlp, &sh, who)) return 0;
+  if (n_rays < 0) {
+    fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
+    return 0;
+  }
+  return ws_layout(n_rays, opts->K, sh.n_params).total;
+}
+
+int svlf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                const svlf_mlp* mlp, const svlf_render_opts* opts, const float* ray_o,
+                const float* ray_d, float* out_rgb, float* out_depth, float* out_acc,
+                void* workspace, size_t ws_bytes, void* stream) {
+  const char* who = "svlf_render";
+  if (out_rgb == nullptr || out_depth == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "out_rgb / out_depth is NULL"));
+  ShadeArgs a{};
+  a.rgb = out_rgb;
+  a.depth = out_depth;
+  a.acc = out_acc;
+  return run_shade(kForward, scenes, n_scenes, ray_offsets_host, mlp, opts, ray_o, ray_d, a,
+                   nullptr, workspace, ws_bytes, stream, who);
+}
+
+int svlf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
+                         const int64_t* ray_offsets_host, const svlf_mlp* mlp,
+                         const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                         const float* grad_rgb, const float* grad_depth, const float* grad_acc,
+                         float* const* grad_features, float* grad_params, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  const char* who = "svlf_render_backward";
+  if (grad_rgb == nullptr || grad_depth == nullptr || grad_params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "grad_rgb / grad_depth / grad_params is NULL"));
+  ShadeArgs a{};
+  a.g_rgb = grad_rgb;
+  a.g_depth = grad_depth;
+  a.g_acc = grad_acc;
+  a.grad_params = grad_params;
+  return run_shade(kBackward, scenes, n_scenes, ray_offsets_host, mlp, opts, ray_o, ray_d, a,
+                   grad_features, workspace, ws_bytes, stream, who);
+}
+
+int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                    const svlf_mlp* mlp, const svlf_render_opts* opts, const float* ray_o,
+                    const float* ray_d, const float* target_rgb, const float* target_depth,
+                    float lambda_depth, float loss_scale, float* out_rgb, float* out_depth,
+                    float* loss_out, float* const* grad_features, float* grad_params,
+                    void* workspace, size_t ws_bytes, void* stream) {
+  const char* who = "svlf_train_step";
+  if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
+  if (!std::isfinite(lambda_depth) || !std::isfinite(loss_scale))
+    return fail(SVLF_E_INVAL, who_str(who, "lambda_depth / loss_scale must be finite"));
+  ShadeArgs a{};
+  a.t_rgb = target_rgb;
+  a.t_depth = target_depth;
+  a.lambda_depth = lambda_depth;
+  a.loss_scale = loss_scale;
+  a.rgb = out_rgb;
+  a.depth = out_depth;
+  a.loss_out = loss_out;
+  a.grad_params = grad_params;
+  return run_shade(kTrain, scenes, n_scenes, ray_offsets_host, mlp, opts, ray_o, ray_d, a,
+                   grad_features, workspace, ws_bytes, stream, who);
+}
+
+int svlf_adam_step(float* param, float* grad, float* m, float* v, int64_t n, float lr,
+                   float beta1, float beta2, float eps, int64_t step_t, uint16_t* bf16_out,
+                   int32_t zero_grad, void* stream) {
+  const char* who = "svlf_adam_step";
+  if (n < 0) return fail(SVLF_E_INVAL, who_str(who, "n < 0"));
+  if (step_t < 1) return fail(SVLF_E_RANGE, who_str(who, "step_t must be >= 1"));
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+      !std::isfinite(lr))
+    return fail(SVLF_E_RANGE, who_str(who, "invalid hyper-parameters"));
+  if (n == 0) return SVLF_OK;
+  if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "NULL array"));
+  const double bc1 = 1.0 - std::pow(static_cast<double>(beta1), static_cast<double>(step_t));
+  const double bc2 = 1.0 - std::pow(static_cast<double>(beta2), static_cast<double>(step_t));
+  hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, static_cast<float>(bc1),
+                             static_cast<float>(bc2), bf16_out, zero_grad,
+                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, who);
+  return SVLF_OK;
+}
+
+int svlf_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream) {
+  if (n < 0) return fail(SVLF_E_INVAL, "svlf_to_bf16: n < 0");
+  if (n == 0) return SVLF_OK;
+  if (src == nullptr || dst == nullptr) return fail(SVLF_E_INVAL, "svlf_to_bf16: NULL array");
+  hipError_t e = launch_to_bf16(src, dst, n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "svlf_to_bf16");
+  return SVLF_OK;
+}
+
+int svlf_fill(float* dst, float value, int64_t n, void* stream) {
+  if (n < 0) return fail(SVLF_E_INVAL, "svlf_fill: n < 0");
+  if (n == 0) return SVLF_OK;
+  if (dst == nullptr) return fail(SVLF_E_INVAL, "svlf_fill: NULL array");
+  hipError_t e = launch_fill(dst, value, n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "svlf_fill");
+  return SVLF_OK;
+}
+
+int svlf_mlp_forward(const svlf_mlp* mlp, const svlf_render_opts* opts, const float* X, int64_t n,
+                     float* out, void* stream) {
+  const char* who = "svlf_mlp_forward";
+  int rc = check_opts(opts, who);
+  if (rc) return rc;
+  MlpShape sh;
+  rc = check_mlp(mlp, &sh, who);
+  if (rc) return rc;
+  if (n < 0) return fail(SVLF_E_INVAL, who_str(who, "n < 0"));
+  if (n == 0) return SVLF_OK;
+  if (X == nullptr || out == nullptr) return fail(SVLF_E_INVAL, who_str(who, "NULL array"));
+  hipError_t e = launch_mlp_forward(mlp->params, sh.C, sh.H, sh.n_hidden, opts->precision, X, n,
+                                    out, static_cast<hipStream_t>(stream));
+  if (e == hipErrorNotSupported)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "no kernel for this MLP shape / precision"));
+  if (e != hipSuccess) return hip_fail(e, who);
+  return SVLF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "svlf.h"
+
+namespace svlf {
+
+// Per-thread error string behind svlf_last_error().
+void set_error(const std::string& msg);
+void clear_error();
+const char* error_cstr();
+
+// One scene as the kernels see it (passed by value in kernel arguments).
+struct DevScene {
+  const svlf_node* nodes;
+  const int32_t* leaf_corners;
+  const float* feat32;
+  const uint16_t* feat16;
+  float* grad;            // backward only
+  int64_t ray_begin;      // first ray of this scene
+  int64_t ray_end;
+  int32_t depth;
+  int32_t block_begin;    // first 256-ray block of this scene in the grid
+};
+
+struct SceneTable {
+  DevScene s[SVLF_MAX_SCENES];
+  int32_t n;
+  int32_t n_blocks;       // total 256-ray blocks over all scenes
+};
+
+// Internal hit record, one per (ray, slot): leaf id, t_in, t_out and the
+// leaf's cell coordinates packed as i | j << 10 | k << 20.
+struct HitRec {
+  int32_t leaf;
+  float tin;
+  float tout;
+  uint32_t ijk;
+};
+
+constexpr int kRaysPerBlock = 256;
+
+// Launchers (defined in the .hip files).
+hipError_t launch_trace_public(const svlf_octree& oct, const float* o, const float* d,
+                               int64_t n, int K, int32_t* leaf, float* tin, float* tout,
+                               int32_t* cnt, hipStream_t s);
+hipError_t launch_trace_internal(const SceneTable& tab, const float* o, const float* d,
+                                 int K, HitRec* hits, int32_t* cnt, hipStream_t s);
+
+struct ShadeArgs {
+  SceneTable tab;
+  const float* o;
+  const float* d;
+  const HitRec* hits;
+  const int32_t* cnt;
+  int32_t K;
+  int32_t tau_mode;
+  int32_t precision;
+  int32_t C;
+  int32_t H;
+  int32_t n_hidden;
+  const float* params;
+  // forward outputs
+  float* rgb;
+  float* depth;
+  float* acc;
+  // backward inputs
+  const float* g_rgb;
+  const float* g_depth;
+  const float* g_acc;
+  // train-step inputs
+  const float* t_rgb;
+  const float* t_depth;
+  float lambda_depth;
+  float loss_scale;
+  float* loss_out;
+  // backward outputs
+  float* grad_params;
+  float* ws_partials;     // [grid][n_params] per-block dW partial sums
+  float* ws_loss;         // [grid] per-block loss partial sums
+  int64_t n_params;
+};
+
+enum ShadeMode { kForward = 0, kBackward = 1, kTrain = 2 };
+
+hipError_t launch_shade(const ShadeArgs& a, int mode, hipStream_t s, int* grid_used);
+size_t shade_workspace_bytes(int64_t n_params, int n_rays_hint);
+int shade_grid_limit();
+
+hipError_t launch_reduce_partials(const float* partials, int rows, int64_t n, float* out,
+                                  const float* loss_partials, float* loss_out, hipStream_t s);
+
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2, uint16_t* bf16, int zero,
+                       hipStream_t s);
+hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t s);
+hipError_t launch_fill(float* dst, float v, int64_t n, hipStream_t s);
+hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, int precision,
+                              const float* X, int64_t n, float* out, hipStream_t s);
+
+// Host octree build (octree_build.cpp).
+struct HostOctree {
+  svlf_octree_sizes sizes;
+  std::vector<svlf_node> nodes;
+  std::vector<int32_t> leaf_corners;
+  std::vector<int32_t> leaf_ijk_sorted;
+};
+int build_octree_host(const int32_t* ijk, int64_t n, int depth, HostOctree* out,
+                      bool want_arrays);
+
+}  // namespace svlf
