@@ -1,0 +1,284 @@
+#!/usr/bin/env python
+"""Benchmark of the SVLF per-ray path on one MI355X.
+
+Workload (the paper-scale one): octree depth 9 (512^3), 40 rotated
+ellipsoids + 20 boxes, surface cells scaled to ~1% occupancy, 32 features per
+vertex (FP32 masters + BF16 copy), decoder 32-64-64-64-4, K = 8, 1600x1600
+views, training batch 2^20 rays sampled from 50 views with analytic targets.
+
+A timed step is one training pass over the batch: traversal, gather +
+trilinear interpolation, decoder, Eq. 3 compositing, MSE + L1 loss and the
+hand-written backward (svlf_train_step) with the BF16 decoder.  Also
+reported: the same step with the FP32 decoder, the forward render of one
+1600^2 view (BF16 and FP32), the dense Adam update timed separately, per-kernel
+durations (HIP events on the launch stream) with the roofline of the
+dominant kernel, PSNR of the BF16 render against the FP64 oracle on a seeded
+ray sample, and the oracle itself timed on the host.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=4096,
+                    help="rays of the batch the oracle trains on for the CPU baseline")
+    ap.add_argument("--psnr-rays", type=int, default=16384)
+    ap.add_argument("--sections", default="all",
+                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr")
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every libsvlf call is
+    queued on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def run(self, fn, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for i in range(steps):
+            fn()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        return float(np.sum(per)), per
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
+                 "(the sharding design is described in DESIGN.md); run with --gpus 1")
+    import torch
+
+    from paper_2205_07058_amd import svlf
+    from synth.configs import get_config
+
+    sections = set(args.sections.split(",")) if args.sections != "all" else {
+        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr"}
+    torch.cuda.set_device(0)
+    svlf.load()
+    t0 = time.time()
+    w = get_config(3)
+    sc = w.scene()
+    log(f"scene: depth {sc.depth}, {sc.leaf_ijk.shape[0]} leaves ({100 * sc.fraction:.2f}%), "
+        f"{sc.n_vertices} vertices ({time.time() - t0:.1f}s)")
+    F = w.features()
+    p = w.params()
+    scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    params = torch.from_numpy(p).cuda()
+    log(f"octree on device: {scene.octree.n_nodes} internal nodes")
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
+    o_v, d_v = w.view_rays(0)
+    log(f"inputs ready: batch {ob.shape[0]} rays, view {o_v.shape[0]} rays ({time.time() - t0:.1f}s)")
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    ob_t, db_t, rgb_tt, dep_tt = T(ob), T(db), T(rgb_t), T(dep_t)
+    ov_t, dv_t = T(o_v), T(d_v)
+    n_b, n_v = ob.shape[0], o_v.shape[0]
+    gF = torch.zeros_like(scene.features)
+    gp = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    ws = svlf.Workspace()
+    timer = Timer(torch)
+    res = {}
+
+    # hits per ray of both ray sets (for the algorithmic byte counts)
+    _, _, _, cnt_b = svlf.trace_hits(scene.octree, ob_t, db_t, w.K)
+    _, _, _, cnt_v = svlf.trace_hits(scene.octree, ov_t, dv_t, w.K)
+    hits_b = int(cnt_b.sum().item())
+    hits_v = int(cnt_v.sum().item())
+    log(f"hits: batch {hits_b} ({hits_b / n_b:.3f}/ray), view {hits_v} ({hits_v / n_v:.3f}/ray)")
+
+    def train_fn(prec, flags=0):
+        opts = svlf.make_opts(w.K, "voxel", prec, flags)
+        return lambda: svlf.train_step([scene], [n_b], params, w.widths, opts, ob_t, db_t, rgb_tt,
+                                       dep_tt, 0.1, 1.0 / n_b, [gF], gp, loss_out=loss, workspace=ws)
+
+    def fwd_fn(prec):
+        opts = svlf.make_opts(w.K, "voxel", prec)
+        out = (torch.empty((n_v, 3), device="cuda"), torch.empty(n_v, device="cuda"),
+               torch.empty(n_v, device="cuda"))
+        return lambda: svlf.render([scene], [n_v], params, w.widths, opts, ov_t, dv_t, *out, workspace=ws)
+
+    for prec in ("bf16", "fp32"):
+        if f"train_{prec}" in sections:
+            ms, _ = timer.run(train_fn(prec), args.steps, args.warmup)
+            res[f"train_{prec}_ms"] = ms / args.steps
+            log(f"train step {prec}: {ms / args.steps:.3f} ms/step, "
+                f"{n_b * args.steps / ms * 1e3 / 1e6:.1f} M rays/s, loss {loss.item():.5f}")
+        if f"fwd_{prec}" in sections:
+            ms, _ = timer.run(fwd_fn(prec), args.steps, args.warmup)
+            res[f"fwd_{prec}_ms"] = ms / args.steps
+            log(f"forward view {prec}: {ms / args.steps:.3f} ms/view, "
+                f"{n_v * args.steps / ms * 1e3 / 1e6:.1f} M rays/s")
+
+    if "adam" in sections:
+        m = torch.zeros_like(scene.features)
+        v = torch.zeros_like(scene.features)
+        st = [0]
+
+        def adam():
+            st[0] += 1
+            svlf.adam_step(scene.features, gF, m, v, 1e-3, 0.9, 0.999, 1e-8, st[0],
+                           bf16_out=scene.features_bf16, zero_grad=True)
+        ms, _ = timer.run(adam, args.steps, args.warmup)
+        res["adam_ms"] = ms / args.steps
+        log(f"dense Adam over {scene.features.numel()} features: {ms / args.steps:.3f} ms")
+        scene.features.copy_(T(F))
+        scene.refresh_bf16()
+
+    stages = {}
+    if "stages" in sections:
+        # split one BF16 train step into its kernels with events between them
+        trace = train_fn("bf16", svlf.FLAG_TRACE_ONLY)
+        shade = train_fn("bf16", svlf.FLAG_REUSE_HITS)
+        trace()
+        ms_tr, _ = timer.run(trace, args.steps, args.warmup)
+        ms_sh, _ = timer.run(shade, args.steps, args.warmup)
+        stages = {"trace_ms": ms_tr / args.steps, "shade_reduce_ms": ms_sh / args.steps}
+        log(f"stages (bf16 train): trace {stages['trace_ms']:.3f} ms, "
+            f"shade+reduce {stages['shade_reduce_ms']:.3f} ms")
+
+    psnr = None
+    if "psnr" in sections:
+        from oracle.octree import Octree
+        from oracle.render import render as oracle_render
+        from oracle.trace import trace_hits as oracle_trace
+        rgb16 = torch.empty((n_v, 3), device="cuda")
+        svlf.render([scene], [n_v], params, w.widths, svlf.make_opts(w.K, "voxel", "bf16"), ov_t, dv_t,
+                    rgb16, torch.empty(n_v, device="cuda"), torch.empty(n_v, device="cuda"), workspace=ws)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(2022)
+        idx = np.sort(rng.choice(n_v, args.psnr_rays, replace=False))
+        t1 = time.time()
+        oc = Octree(sc.leaf_ijk, sc.depth)
+        log(f"oracle octree built ({time.time() - t1:.1f}s)")
+        hits = oracle_trace(oc, o_v[idx], d_v[idx], w.K)
+        er, _, _, _ = oracle_render(oc, F, p, w.widths, o_v[idx], d_v[idx], hits)
+        got = rgb16.cpu().numpy()[idx]
+        mse = float(np.mean((got.astype(np.float64) - er) ** 2))
+        psnr = float("inf") if mse == 0 else -10.0 * np.log10(mse)
+        log(f"PSNR bf16 render vs FP64 oracle on {args.psnr_rays} rays: {psnr:.2f} dB")
+        res["oracle_octree"] = oc
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, sc, F, p, ob, db, rgb_t, dep_t, args.cpu_rays, res.get("oracle_octree"))
+
+    # roofline of the dominant kernel (the fused shading kernel of the BF16
+    # train step): algorithmic bytes per launch over its event-timed duration
+    C = w.C
+    n_params = p.size
+    grid = 256                                    # one block per CU for the BF16 train kernel
+    bytes_ray = 24 + 4 + 16                      # o, d, hit count, targets
+    bytes_hit = 16 + 32 + 8 * C * 2 + 8 * C * 4 * 2   # hit record, corners, BF16 rows, FP32 grad RMW
+    bytes_launch = n_b * bytes_ray + hits_b * bytes_hit + grid * n_params * 4
+    roof = None
+    if stages:
+        sh_ms = stages["shade_reduce_ms"]
+        achieved = bytes_launch / (sh_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_shade<bf16,32,64,3,train> + k_reduce",
+                "bytes_per_launch": int(bytes_launch),
+                "bytes_per_hit": bytes_hit, "bytes_per_ray": bytes_ray, "hits_per_ray": round(hits_b / n_b, 4)}
+
+    ms = res.get("train_bf16_ms")
+    value = n_b / (ms * 1e-3) if ms else None
+    out = {
+        "metric": "rays/sec train step @1600^2 workload (BF16 decoder on MFMA); fwd render, FP32 path and PSNR vs FP64 oracle alongside",
+        "value": round(value, 1) if value else None,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4) if ms else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded analytic scene and targets standing in for RTMV)",
+        "config": {"workload": "depth-9 octree (512^3), 40 ellipsoids + 20 boxes, ~1% surface leaves, "
+                               "C=32, MLP 32-64-64-64-4, K=8, batch 2^20 rays from 50 1600^2 views",
+                   "batch": n_b, "view_rays": n_v, "leaves": int(sc.leaf_ijk.shape[0]),
+                   "vertices": int(sc.n_vertices), "hits_per_ray_batch": round(hits_b / n_b, 4),
+                   "hits_per_ray_view": round(hits_v / n_v, 4)},
+        "step": "traversal + gather + decoder + Eq. 3 + loss + backward (svlf_train_step); Adam separate",
+        "train_fp32_rays_per_s": round(n_b / (res["train_fp32_ms"] * 1e-3), 1) if "train_fp32_ms" in res else None,
+        "fwd_view_bf16_rays_per_s": round(n_v / (res["fwd_bf16_ms"] * 1e-3), 1) if "fwd_bf16_ms" in res else None,
+        "fwd_view_fp32_rays_per_s": round(n_v / (res["fwd_fp32_ms"] * 1e-3), 1) if "fwd_fp32_ms" in res else None,
+        "adam_dense_ms": round(res["adam_ms"], 4) if "adam_ms" in res else None,
+        "train_bf16_with_adam_rays_per_s": round(n_b / ((res["train_bf16_ms"] + res["adam_ms"]) * 1e-3), 1)
+        if "adam_ms" in res and ms else None,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
+        "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paper_context": "SVLF renders 0.08 s/frame on one RTX 3090 and trains 30K steps in 2.7 h on one V100 (Table 6)",
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, sc, F, p, ob, db, rgb_t, dep_t, n_rays, oc=None):
+    """The FP64 oracle (trace + render + loss + hand-written backward) on a
+    seeded sample of the training batch, timed on the host."""
+    from oracle.octree import Octree
+    from oracle.render import loss as oracle_loss, render as oracle_render, render_backward
+    from oracle.trace import trace_hits as oracle_trace
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    if oc is None:
+        t1 = time.time()
+        oc = Octree(sc.leaf_ijk, sc.depth)
+        log(f"oracle octree built ({time.time() - t1:.1f}s)")
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(ob.shape[0], n_rays, replace=False))
+    o, d = ob[idx], db[idx]
+    t0 = time.time()
+    hits = oracle_trace(oc, o, d, w.K)
+    rgb, dep, acc, st = oracle_render(oc, F, p, w.widths, o, d, hits)
+    L, g_rgb, g_dep = oracle_loss(rgb, dep, rgb_t[idx], dep_t[idx])
+    gF, gp = render_backward(st, g_rgb, g_dep)
+    dt = time.time() - t0
+    log(f"oracle train pass on {n_rays} rays: {dt:.2f}s ({n_rays / dt:.0f} rays/s, {threads} threads)")
+    return {"value": round(n_rays / dt, 2), "unit": "rays/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_rays} seeded rays of the 2^20-ray batch: FP64 oracle trace + render + loss + "
+                      f"backward, single process (numpy, BLAS threads = {threads}); octree build excluded"}
+
+
+if __name__ == "__main__":
+    main()

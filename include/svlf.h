@@ -132,8 +132,9 @@ typedef struct {
 
 /* The decoder.  widths[0] = C, widths[n_layers] = 4, hidden layers ReLU.
  * params: device FP32, per layer W[out][in] row-major then b[out], layers
- * concatenated (n = sum out*in + out).  Supported shapes: C in {8,16,32},
- * all hidden widths equal H in {32,64}, 1..4 hidden layers. */
+ * concatenated (n = sum out*in + out).  Supported shapes (C, hidden width,
+ * hidden layers): (8, 32, 2), (16, 64, 3), (32, 64, 3); other shapes return
+ * SVLF_E_UNSUPPORTED from the render calls. */
 typedef struct {
   int32_t n_layers;
   int32_t widths[SVLF_MAX_LAYERS + 1];
@@ -152,8 +153,17 @@ typedef struct {
                                     with FP32 accumulation; traversal, slabs,
                                     interpolation weights, compositing and
                                     gradient accumulation stay FP32          */
-  int32_t reserved;              /* must be 0                                */
+  int32_t flags;                 /* 0, or SVLF_FLAG_* bits                   */
 } svlf_render_opts;
+
+/* svlf_render_opts.flags.  SVLF_FLAG_TRACE_ONLY runs only the traversal,
+ * leaving the hit slots and counts in the workspace; SVLF_FLAG_REUSE_HITS
+ * skips the traversal and shades the hits left in the workspace by an
+ * earlier call with the same scenes, rays, ray_offsets and K (the caller
+ * guarantees this; nothing is checked).  Together they split one call into
+ * its two kernels, e.g. to reuse one traversal for several evaluations. */
+#define SVLF_FLAG_TRACE_ONLY 1
+#define SVLF_FLAG_REUSE_HITS 2
 
 /* ---------------------------------------------------------------- octree */
 

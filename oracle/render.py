@@ -19,8 +19,9 @@ Follows SVLF section 4 with the single-decoder reading used by the library:
 
 ``bf16=True`` rounds (round to nearest even) the features, the weights, the
 MLP input x and every hidden activation after ReLU to bfloat16 before use;
-in the backward it also rounds each layer's incoming gradient before the
-products.  All accumulation stays in FP64.
+in the backward it also rounds each layer's incoming gradient (dL/dz) to
+bfloat16 before it enters the weight, bias and input gradients.  All
+accumulation stays in FP64.
 
 No GPU code and no automatic differentiation is used; the backward is
 derived by hand from the formulas above.
@@ -188,7 +189,7 @@ def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
         W, b = layers[li]
         a = st.acts[li]
         g_zr = r(g_z)
-        grads.append((g_zr.T @ a, np.sum(g_z, axis=0)))
+        grads.append((g_zr.T @ a, np.sum(g_zr, axis=0)))
         g_a = g_zr @ r(W)
         if li > 0:
             g_z = np.where(st.pres[li - 1] > 0.0, g_a, 0.0)

@@ -90,7 +90,10 @@ int check_opts(const svlf_render_opts* opts, const char* who) {
     return fail(SVLF_E_RANGE, who_str(who, "unknown tau_mode"));
   if (opts->precision != SVLF_FP32 && opts->precision != SVLF_BF16)
     return fail(SVLF_E_RANGE, who_str(who, "unknown precision"));
-  if (opts->reserved != 0) return fail(SVLF_E_INVAL, who_str(who, "reserved must be 0"));
+  if (opts->flags & ~(SVLF_FLAG_TRACE_ONLY | SVLF_FLAG_REUSE_HITS))
+    return fail(SVLF_E_INVAL, who_str(who, "unknown flags"));
+  if ((opts->flags & SVLF_FLAG_TRACE_ONLY) && (opts->flags & SVLF_FLAG_REUSE_HITS))
+    return fail(SVLF_E_INVAL, who_str(who, "TRACE_ONLY and REUSE_HITS exclude each other"));
   return SVLF_OK;
 }
 
@@ -198,9 +201,13 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   a.params = mlp->params;
   a.n_params = sh.n_params;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_trace_internal(a.tab, ray_o, ray_d, opts->K, const_cast<HitRec*>(a.hits),
-                                       const_cast<int32_t*>(a.cnt), s);
-  if (e != hipSuccess) return hip_fail(e, who);
+  hipError_t e = hipSuccess;
+  if (!(opts->flags & SVLF_FLAG_REUSE_HITS)) {
+    e = launch_trace_internal(a.tab, ray_o, ray_d, opts->K, const_cast<HitRec*>(a.hits),
+                              const_cast<int32_t*>(a.cnt), s);
+    if (e != hipSuccess) return hip_fail(e, who);
+  }
+  if (opts->flags & SVLF_FLAG_TRACE_ONLY) return SVLF_OK;
   int grid = 0;
   e = launch_shade(a, mode, s, &grid);
   if (e == hipErrorNotSupported)

@@ -1,19 +1,915 @@
-// Shading kernels (placeholder until the fused kernels land).
+// Shading kernels of the SVLF per-ray path (gfx950).
+//
+// For every hit (leaf, t_in, t_out) found by the traversal: trilinear
+// interpolation of the leaf's corner features at the segment midpoint
+// (section 4.1), one ReLU decoder C -> H ... -> 4 (section 4.5), optical
+// thickness from sigma (section 4 footnote) and front-to-back alpha
+// compositing (Eq. 3); the backward variant recomputes all of it and
+// propagates dL/d(rgb, depth, acc) to the features (FP32 atomics) and the
+// decoder parameters (per-block partial sums, reduced deterministically).
+//
+// Organisation (one block = 4 waves = 256 rays per work item, persistent):
+//  * the rays' hits are consumed in windows of up to WIN hits that never
+//    split a ray, so compositing and its backward are window-local;
+//  * the window's hit records and the interpolated MLP inputs live in LDS;
+//    each wave runs the decoder on a 32-hit tile with MFMA (32x32x16 BF16 or
+//    32x32x2 FP32), hits on the N dimension: a layer's result (D layout:
+//    lane = hit, registers = output features) is fed to the next layer's B
+//    operand directly, the K order of every weight matrix being permuted at
+//    pack time to match the D layout (no shuffles between layers);
+//  * backward: dL/dz of each layer and the layer's input are written to LDS
+//    transposed ([feature][hit]) and every wave accumulates the dW tiles it
+//    owns over all windows in registers (K = hits); the data gradient uses a
+//    second, transposed weight pack.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
 
 #include "svlf_internal.hpp"
 
 namespace svlf {
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kWaves = 4;
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// FP32 -> bfloat16 bits, round to nearest even.
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return static_cast<short>((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+__device__ __forceinline__ f32x16 mma(s16x8 a, s16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mma(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x16 zero16() {
+  f32x16 z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = 0.0f;
+  return z;
+}
+
+// Row (output feature within a 32-tile) of register i of a 32x32 MFMA result
+// held by a lane of group g = lane / 32.
+__device__ __forceinline__ constexpr int drow(int i, int g) { return 8 * (i >> 2) + 4 * g + (i & 3); }
+
+// ------------------------------------------------------------ geometry
+
+constexpr int in_w(int l, int CI, int H) { return l == 0 ? CI : H; }
+constexpr int out_w(int l, int H, int NH) { return l == NH ? 32 : H; }
+constexpr int in_real(int l, int C, int H) { return l == 0 ? C : H; }
+constexpr int out_real(int l, int H, int NH) { return l == NH ? 4 : H; }
+constexpr int bwd_m(int l, int H) { return l == 0 ? 32 : H; }
+
+constexpr int fwd_off(int l, int CI, int H, int NH) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += out_w(i, H, NH) * in_w(i, CI, H);
+  return o;
+}
+constexpr int bwd_off(int l, int H, int NH) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += bwd_m(i, H) * out_w(i, H, NH);
+  return o;
+}
+constexpr int bias_off(int l, int H, int NH) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += out_w(i, H, NH);
+  return o;
+}
+constexpr int par_w(int l, int C, int H, int NH) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += out_real(i, H, NH) * in_real(i, C, H) + out_real(i, H, NH);
+  return o;
+}
+constexpr int par_b(int l, int C, int H, int NH) {
+  return par_w(l, C, H, NH) + out_real(l, H, NH) * in_real(l, C, H);
+}
+// dW tiles per layer: (out tiles) x (in tiles)
+constexpr int dw_mt(int l, int H, int NH) { return out_w(l, H, NH) / 32; }
+constexpr int dw_nt(int l, int H) { return l == 0 ? 1 : H / 32; }
+constexpr int dw_tile_off(int l, int H, int NH) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += dw_mt(i, H, NH) * dw_nt(i, H);
+  return o;
+}
+constexpr int align16(int x) { return (x + 15) & ~15; }
+
+template <int P, int C_, int H_, int NH_, int MODE_>
+struct Cfg {
+  static constexpr bool BF = P == 1;
+  static constexpr int C = C_, H = H_, NH = NH_, MODE = MODE_;
+  static constexpr bool BWD = MODE != kForward;
+  static constexpr int KS = BF ? 16 : 2;            // K per MFMA
+  static constexpr int CI = (BF && C < 16) ? 16 : C;  // padded decoder input
+  static constexpr int NL = NH + 1;
+  static constexpr int MTH = H / 32;
+  static constexpr int WIN = (BWD && !BF) ? 64 : 128;
+  static constexpr int NTILE = WIN / 32;
+  static constexpr int EB = BF ? 2 : 4;
+  using Op = typename std::conditional<BF, s16x8, float>::type;
+  using Elem = typename std::conditional<BF, uint16_t, float>::type;
+  static constexpr int FWD_ELEMS = fwd_off(NL, CI, H, NH);
+  static constexpr int BWD_ELEMS = BWD ? bwd_off(NL, H, NH) : 0;
+  static constexpr int BIAS_ELEMS = bias_off(NL, H, NH);
+  static constexpr int NPARAMS = par_w(NL, C, H, NH);
+  static constexpr int NDW = dw_tile_off(NL, H, NH);          // dW tiles
+  static constexpr int DW_SLOTS = (NDW + kWaves - 1) / kWaves;
+  static constexpr int NBIAS = NH * H + 4;
+  static constexpr int XS = CI + (BF ? 8 : 4);                  // X row stride
+  static constexpr int TS = WIN + (BF ? 8 : 1);                 // transposed row stride
+  static constexpr int TROWS = H > 32 ? H : 32;
+  // LDS byte layout
+  static constexpr int L_FP = 0;
+  static constexpr int L_BP = align16(L_FP + FWD_ELEMS * EB);
+  static constexpr int L_BI = align16(L_BP + BWD_ELEMS * EB);
+  static constexpr int L_REC = align16(L_BI + BIAS_ELEMS * 4);
+  static constexpr int L_X = align16(L_REC + WIN * 32);
+  static constexpr int L_OUT = align16(L_X + WIN * XS * EB);
+  static constexpr int L_GZ = align16(L_OUT + WIN * 16);
+  static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
+  static constexpr int L_SCR = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
+  static constexpr int LDS_BYTES = L_SCR + 64;
+  static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+};
+
+// Hit record in LDS (32 bytes).
+struct RecL {
+  int32_t leaf;
+  float ux, uy, uz;
+  float tmid;
+  float dt;
+  float T;
+  float pad;
+};
+
+// K index of step s, lane group g, element j for an operand that comes from
+// a 32x32 result tile (D layout, see drow).
+template <bool BF>
+__device__ __forceinline__ int kmap_d(int s, int g, int j) {
+  if (BF) return 32 * (s >> 1) + 8 * (2 * (s & 1) + (j >> 2)) + 4 * g + (j & 3);
+  return 32 * (s >> 4) + 8 * ((s & 15) >> 2) + 4 * g + (s & 3);
+}
+// K index of the first layer (operand read from the X tile in LDS).
+template <bool BF>
+__device__ __forceinline__ int kmap_x(int s, int g, int j) {
+  if (BF) return 16 * s + 8 * g + j;
+  return 4 * (2 * (s >> 2) + g) + (s & 3);
+}
+
+template <class CF>
+struct Smem {
+  char* base;
+  __device__ typename CF::Elem* fpack() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_FP); }
+  __device__ typename CF::Elem* bpack() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_BP); }
+  __device__ float* bias() const { return reinterpret_cast<float*>(base + CF::L_BI); }
+  __device__ RecL* rec() const { return reinterpret_cast<RecL*>(base + CF::L_REC); }
+  __device__ typename CF::Elem* X() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_X); }
+  __device__ float* out() const { return reinterpret_cast<float*>(base + CF::L_OUT); }
+  __device__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_GZ); }
+  __device__ typename CF::Elem* AT() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_AT); }
+  __device__ int* scr() const { return reinterpret_cast<int*>(base + CF::L_SCR); }
+};
+
+template <class CF>
+__device__ __forceinline__ typename CF::Elem to_elem(float v) {
+  if constexpr (CF::BF) return static_cast<uint16_t>(bf16_rne(v));
+  else return v;
+}
+
+// ------------------------------------------------------------ weight packs
+
+template <class CF>
+__device__ void build_packs(const Smem<CF>& sm, const float* __restrict__ params) {
+  constexpr int E = CF::BF ? 8 : 1;
+  static_for<CF::NL>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    constexpr int IW = in_w(l, CF::CI, CF::H), OW = out_w(l, CF::H, CF::NH);
+    constexpr int IR = in_real(l, CF::C, CF::H), OR = out_real(l, CF::H, CF::NH);
+    constexpr int STEPS = IW / CF::KS;
+    const float* W = params + par_w(l, CF::C, CF::H, CF::NH);
+    const float* b = params + par_b(l, CF::C, CF::H, CF::NH);
+    typename CF::Elem* fp = sm.fpack() + fwd_off(l, CF::CI, CF::H, CF::NH);
+    for (int e = threadIdx.x; e < OW * IW; e += kThreads) {
+      const int j = e % E, lane = (e / E) % 64, s = (e / (E * 64)) % STEPS, mt = e / (E * 64 * STEPS);
+      const int m = 32 * mt + (lane & 31), g = lane >> 5;
+      const int k = (l == 0) ? kmap_x<CF::BF>(s, g, j) : kmap_d<CF::BF>(s, g, j);
+      fp[e] = to_elem<CF>((m < OR && k < IR) ? W[m * IR + k] : 0.0f);
+    }
+    for (int r = threadIdx.x; r < OW; r += kThreads)
+      sm.bias()[bias_off(l, CF::H, CF::NH) + r] = r < OR ? b[r] : 0.0f;
+    if constexpr (CF::BWD) {
+      // transposed pack: M = layer input (padded), K = layer output (D layout)
+      constexpr int BM = bwd_m(l, CF::H), BSTEPS = OW / CF::KS;
+      typename CF::Elem* bp = sm.bpack() + bwd_off(l, CF::H, CF::NH);
+      for (int e = threadIdx.x; e < BM * OW; e += kThreads) {
+        const int j = e % E, lane = (e / E) % 64, s = (e / (E * 64)) % BSTEPS, mt = e / (E * 64 * BSTEPS);
+        const int m = 32 * mt + (lane & 31), g = lane >> 5;
+        const int k = kmap_d<CF::BF>(s, g, j);
+        bp[e] = to_elem<CF>((m < IR && k < OR) ? W[k * IR + m] : 0.0f);
+      }
+    }
+  });
+}
+
+template <class CF>
+__device__ __forceinline__ typename CF::Op pack_operand(const typename CF::Elem* pack, int mt, int s,
+                                                        int steps, int lane) {
+  if constexpr (CF::BF)
+    return *reinterpret_cast<const s16x8*>(pack + ((mt * steps + s) * 64 + lane) * 8);
+  else
+    return pack[(mt * steps + s) * 64 + lane];
+}
+
+template <class CF>
+__device__ __forceinline__ typename CF::Op d_operand(const f32x16* t, int s) {
+  if constexpr (CF::BF) {
+    s16x8 b;
+    const f32x16& tt = t[s >> 1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = bf16_rne(tt[8 * (s & 1) + j]);
+    return b;
+  } else {
+    return t[s >> 4][s & 15];
+  }
+}
+
+template <class CF>
+__device__ __forceinline__ typename CF::Op x_operand(const Smem<CF>& sm, int row, int s, int g) {
+  if constexpr (CF::BF) {
+    return *reinterpret_cast<const s16x8*>(sm.X() + row * CF::XS + 16 * s + 8 * g);
+  } else {
+    return sm.X()[row * CF::XS + 4 * (2 * (s >> 2) + g) + (s & 3)];
+  }
+}
+
+template <class CF>
+__device__ __forceinline__ f32x16 bias_tile(const Smem<CF>& sm, int l_off, int mt, int g) {
+  f32x16 t;
+  const float* b = sm.bias() + l_off + 32 * mt + 4 * g;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(b + 8 * q);
+    t[4 * q + 0] = v[0];
+    t[4 * q + 1] = v[1];
+    t[4 * q + 2] = v[2];
+    t[4 * q + 3] = v[3];
+  }
+  return t;
+}
+
+__device__ __forceinline__ void relu16(f32x16& t) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = t[i] > 0.0f ? t[i] : 0.0f;
+}
+
+// Decoder forward on the 32 hits [n0, n0+32) of the window.  Returns the
+// output tile (rows 0..3 = raw o_0..o_3 in registers 0..3 of lanes 0..31);
+// with SAVE, the post-ReLU activations of every hidden layer are kept.
+template <class CF, bool SAVE>
+__device__ __forceinline__ f32x16 mlp_tile(const Smem<CF>& sm, int n0, int lane,
+                                           f32x16 (&act)[CF::NH][CF::MTH]) {
+  const int g = lane >> 5, row = n0 + (lane & 31);
+  f32x16 cur[CF::MTH];
+  {
+    constexpr int S0 = CF::CI / CF::KS;
+    const typename CF::Elem* A = sm.fpack();
+#pragma unroll
+    for (int mt = 0; mt < CF::MTH; ++mt) cur[mt] = bias_tile(sm, 0, mt, g);
+#pragma unroll
+    for (int s = 0; s < S0; ++s) {
+      const typename CF::Op b = x_operand(sm, row, s, g);
+#pragma unroll
+      for (int mt = 0; mt < CF::MTH; ++mt) cur[mt] = mma(pack_operand<CF>(A, mt, s, S0, lane), b, cur[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < CF::MTH; ++mt) relu16(cur[mt]);
+    if constexpr (SAVE) {
+#pragma unroll
+      for (int mt = 0; mt < CF::MTH; ++mt) act[0][mt] = cur[mt];
+    }
+  }
+  static_for<CF::NH - 1>([&](auto lc) {
+    constexpr int l = decltype(lc)::value + 1;
+    constexpr int S = CF::H / CF::KS;
+    const typename CF::Elem* A = sm.fpack() + fwd_off(l, CF::CI, CF::H, CF::NH);
+    f32x16 nxt[CF::MTH];
+#pragma unroll
+    for (int mt = 0; mt < CF::MTH; ++mt) nxt[mt] = bias_tile(sm, bias_off(l, CF::H, CF::NH), mt, g);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const typename CF::Op b = d_operand<CF>(cur, s);
+#pragma unroll
+      for (int mt = 0; mt < CF::MTH; ++mt) nxt[mt] = mma(pack_operand<CF>(A, mt, s, S, lane), b, nxt[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < CF::MTH; ++mt) {
+      relu16(nxt[mt]);
+      cur[mt] = nxt[mt];
+      if constexpr (SAVE) act[l][mt] = nxt[mt];
+    }
+  });
+  constexpr int S = CF::H / CF::KS;
+  const typename CF::Elem* A = sm.fpack() + fwd_off(CF::NH, CF::CI, CF::H, CF::NH);
+  f32x16 o = bias_tile(sm, bias_off(CF::NH, CF::H, CF::NH), 0, g);
+#pragma unroll
+  for (int s = 0; s < S; ++s) o = mma(pack_operand<CF>(A, 0, s, S, lane), d_operand<CF>(cur, s), o);
+  return o;
+}
+
+// Data gradient through layer l: r = W_l^T gt (gt in D layout over the
+// layer's outputs, r in D layout over its inputs).
+template <class CF, int l>
+__device__ __forceinline__ void bwd_data(const Smem<CF>& sm, const f32x16* gt, f32x16* r, int lane) {
+  constexpr int MT = bwd_m(l, CF::H) / 32;
+  constexpr int S = out_w(l, CF::H, CF::NH) / CF::KS;
+  const typename CF::Elem* B = sm.bpack() + bwd_off(l, CF::H, CF::NH);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) r[mt] = zero16();
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const typename CF::Op b = d_operand<CF>(gt, s);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) r[mt] = mma(pack_operand<CF>(B, mt, s, S, lane), b, r[mt]);
+  }
+}
+
+// Writes `nt` D-layout tiles of the hits [n0, n0+32) transposed into T
+// ([feature][hit], row stride TS).
+template <class CF, int NT>
+__device__ __forceinline__ void store_T(typename CF::Elem* T, const f32x16* t, int n0, int lane) {
+  const int g = lane >> 5, col = n0 + (lane & 31);
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) T[(32 * mt + drow(i, g)) * CF::TS + col] = to_elem<CF>(t[mt][i]);
+  }
+}
+
+// ------------------------------------------------------------ block helpers
+
+__device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) scr[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const int t = scr[i];
+    pre += (i < w) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+__device__ __forceinline__ float block_sum(float v, float* scr) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) scr[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float t = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t += scr[i];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// ------------------------------------------------------------ the kernel
+
+template <class CF>
+__global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  const Smem<CF> sm{smem_raw};
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
+
+  build_packs<CF>(sm, a.params);
+
+  // dW tiles owned by this wave (accumulated over everything this block does)
+  f32x16 dw[CF::DW_SLOTS > 0 ? CF::DW_SLOTS : 1];
+#pragma unroll
+  for (int i = 0; i < CF::DW_SLOTS; ++i) dw[i] = zero16();
+  float db = 0.0f;
+  int db_layer = -1, db_row = 0;
+  if (CF::BWD && tid < CF::NBIAS) {
+    db_layer = tid / CF::H;
+    db_row = tid % CF::H;
+    if (db_layer > CF::NH) db_layer = CF::NH;
+  }
+  float loss_acc = 0.0f;
+
+  // XCD-aware item ranges: blocks of one XCD get neighbouring ray blocks
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int NB = a.tab.n_blocks;
+  const int per = (NB + G - 1) / G;
+  const int it_begin = lb * per, it_end = min(NB, (lb + 1) * per);
+
+  __syncthreads();
+
+  for (int item = it_begin; item < it_end; ++item) {
+    int si = 0;
+    while (si + 1 < a.tab.n && item >= a.tab.s[si + 1].block_begin) ++si;
+    const DevScene& sc = a.tab.s[si];
+    const int64_t r = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads + tid;
+    const bool live = r < sc.ray_end;
+    const int count = live ? a.cnt[r] : 0;
+    const float h = __int_as_float((128 - sc.depth) << 23);       // 2^(1-depth)
+    const float inv_h = __int_as_float((126 + sc.depth) << 23);   // 2^(depth-1)
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0;
+    if (live && count > 0) {
+      ox = a.o[3 * r]; oy = a.o[3 * r + 1]; oz = a.o[3 * r + 2];
+      dx = a.d[3 * r]; dy = a.d[3 * r + 1]; dz = a.d[3 * r + 2];
+    }
+    int total;
+    const int off = block_excl_scan(count, sm.scr(), total);
+    float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, acc = 0.0f;
+
+    int s0 = 0;
+    while (s0 < total) {
+      // the window: rays whose hits all fit in [s0, s0 + WIN)
+      if (tid == 0) sm.scr()[8] = total;
+      __syncthreads();
+      const bool started = count > 0 && off >= s0;
+      const bool in_win = started && off + count <= s0 + CF::WIN;
+      if (started && !in_win) atomicMin(&sm.scr()[8], off);
+      __syncthreads();
+      const int s1 = sm.scr()[8];
+      const int tw = s1 - s0;
+      if (in_win) {
+        const HitRec* hr = a.hits + r * a.K;
+        for (int q = 0; q < count; ++q) {
+          const HitRec hh = hr[q];
+          const float tm = 0.5f * (hh.tin + hh.tout);
+          const float lx = -1.0f + static_cast<float>(hh.ijk & 1023u) * h;
+          const float ly = -1.0f + static_cast<float>((hh.ijk >> 10) & 1023u) * h;
+          const float lz = -1.0f + static_cast<float>(hh.ijk >> 20) * h;
+          RecL rc;
+          rc.leaf = hh.leaf;
+          rc.ux = fminf(fmaxf((ox + tm * dx - lx) * inv_h, 0.0f), 1.0f);
+          rc.uy = fminf(fmaxf((oy + tm * dy - ly) * inv_h, 0.0f), 1.0f);
+          rc.uz = fminf(fmaxf((oz + tm * dz - lz) * inv_h, 0.0f), 1.0f);
+          rc.tmid = tm;
+          rc.dt = hh.tout - hh.tin;
+          rc.T = 0.0f;
+          rc.pad = 0.0f;
+          sm.rec()[off - s0 + q] = rc;
+        }
+      }
+      __syncthreads();
+
+      // gather + trilinear interpolation -> X[h][0..CI)
+      {
+        constexpr int ROWB = CF::C * CF::EB;
+        constexpr int TPH = ROWB / 16;
+        constexpr int VPT = 16 / CF::EB;           // values per thread
+        constexpr int HPP = kThreads / TPH;
+        const int q = tid % TPH;
+        for (int hb = 0; hb < CF::WIN; hb += HPP) {
+          const int hh = hb + tid / TPH;
+          if (hh >= CF::WIN) break;
+          float v[VPT];
+#pragma unroll
+          for (int i = 0; i < VPT; ++i) v[i] = 0.0f;
+          if (hh < tw) {
+            const RecL rc = sm.rec()[hh];
+            const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(rc.leaf));
+            const int4 c0 = lc[0], c1 = lc[1];
+            const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
+                        wz[2] = {1.0f - rc.uz, rc.uz};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
+              if constexpr (CF::BF) {
+                const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * CF::C + 8 * q);
+                const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  v[2 * i] += wj * bf16_f32(static_cast<uint16_t>(w4[i] & 0xFFFFu));
+                  v[2 * i + 1] += wj * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
+                }
+              } else {
+                const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * CF::C + 4 * q);
+                v[0] += wj * f.x;
+                v[1] += wj * f.y;
+                v[2] += wj * f.z;
+                v[3] += wj * f.w;
+              }
+            }
+          }
+          typename CF::Elem* xr = sm.X() + hh * CF::XS + VPT * q;
+#pragma unroll
+          for (int i = 0; i < VPT; ++i) xr[i] = to_elem<CF>(v[i]);
+          if (CF::CI > CF::C && q == 0) {
+#pragma unroll
+            for (int i = CF::C; i < CF::CI; ++i) sm.X()[hh * CF::XS + i] = to_elem<CF>(0.0f);
+          }
+        }
+      }
+      __syncthreads();
+
+      // decoder on the window: one 32-hit tile per wave
+      f32x16 act[CF::NH][CF::MTH];
+      const int n0 = 32 * wave;
+      const bool has_tile = wave < CF::NTILE && n0 < tw;
+      if (has_tile) {
+        const f32x16 o = mlp_tile<CF, CF::BWD>(sm, n0, lane, act);
+        if (g == 0) {
+          const f32x4 ov = {o[0], o[1], o[2], o[3]};
+          *reinterpret_cast<f32x4*>(sm.out() + 4 * (n0 + lane)) = ov;
+        }
+      }
+      __syncthreads();
+
+      // Eq. 3 front to back (owner lanes), and its backward
+      if (in_win) {
+        const int p0 = off - s0;
+        float T = 1.0f;
+        for (int q = 0; q < count; ++q) {
+          const f32x4 o = *reinterpret_cast<const f32x4*>(sm.out() + 4 * (p0 + q));
+          RecL& rc = sm.rec()[p0 + q];
+          const float sig = fmaxf(o[3], 0.0f);
+          const float ft = a.tau_mode == SVLF_TAU_VOXEL ? rc.dt * inv_h
+                           : a.tau_mode == SVLF_TAU_WORLD ? rc.dt : 1.0f;
+          const float tau = sig * ft;
+          const float w = T * -expm1f(-tau);
+          cr += w * sigmoidf_(o[0]);
+          cg += w * sigmoidf_(o[1]);
+          cb += w * sigmoidf_(o[2]);
+          dep += w * rc.tmid;
+          acc += w;
+          if constexpr (CF::BWD) rc.T = T;
+          T *= expf(-tau);
+        }
+        if constexpr (CF::BWD) {
+          float gr, gg, gb, gd, ga;
+          if (CF::MODE == kTrain) {
+            const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
+                        eb = cb - a.t_rgb[3 * r + 2], ed = dep - a.t_depth[r];
+            const float k2 = a.loss_scale * (2.0f / 3.0f);
+            gr = k2 * er;
+            gg = k2 * eg;
+            gb = k2 * eb;
+            gd = a.loss_scale * a.lambda_depth * (ed > 0.0f ? 1.0f : (ed < 0.0f ? -1.0f : 0.0f));
+            ga = 0.0f;
+          } else {
+            gr = a.g_rgb[3 * r];
+            gg = a.g_rgb[3 * r + 1];
+            gb = a.g_rgb[3 * r + 2];
+            gd = a.g_depth[r];
+            ga = a.g_acc ? a.g_acc[r] : 0.0f;
+          }
+          float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f, St = 0.0f, Sa = 0.0f;
+          for (int q = count - 1; q >= 0; --q) {
+            float* op = sm.out() + 4 * (p0 + q);
+            const f32x4 o = *reinterpret_cast<const f32x4*>(op);
+            const RecL rc = sm.rec()[p0 + q];
+            const float sig = fmaxf(o[3], 0.0f);
+            const float ft = a.tau_mode == SVLF_TAU_VOXEL ? rc.dt * inv_h
+                             : a.tau_mode == SVLF_TAU_WORLD ? rc.dt : 1.0f;
+            const float tau = sig * ft;
+            const float e = expf(-tau);
+            const float w = rc.T * -expm1f(-tau);
+            const float Tn = rc.T * e;
+            const float c0 = sigmoidf_(o[0]), c1 = sigmoidf_(o[1]), c2 = sigmoidf_(o[2]);
+            const float gtau = gr * (Tn * c0 - Sr) + gg * (Tn * c1 - Sg) + gb * (Tn * c2 - Sb) +
+                               gd * (Tn * rc.tmid - St) + ga * (Tn - Sa);
+            Sr += w * c0;
+            Sg += w * c1;
+            Sb += w * c2;
+            St += w * rc.tmid;
+            Sa += w;
+            f32x4 go;
+            go[0] = gr * w * c0 * (1.0f - c0);
+            go[1] = gg * w * c1 * (1.0f - c1);
+            go[2] = gb * w * c2 * (1.0f - c2);
+            go[3] = o[3] > 0.0f ? gtau * ft : 0.0f;
+            *reinterpret_cast<f32x4*>(op) = go;
+          }
+        }
+      }
+
+      if constexpr (CF::BWD) {
+        __syncthreads();
+        // output-layer gradient tile (rows 0..3 = dL/do, zero elsewhere)
+        f32x16 gz[CF::MTH];
+#pragma unroll
+        for (int mt = 0; mt < CF::MTH; ++mt) gz[mt] = zero16();
+        if (has_tile && g == 0 && n0 + lane < tw) {
+          const f32x4 go = *reinterpret_cast<const f32x4*>(sm.out() + 4 * (n0 + lane));
+          gz[0][0] = go[0];
+          gz[0][1] = go[1];
+          gz[0][2] = go[2];
+          gz[0][3] = go[3];
+        }
+        f32x16 gx[1];
+        static_for<CF::NL>([&](auto lc) {
+          constexpr int l = CF::NH - decltype(lc)::value;
+          constexpr int OT = out_w(l, CF::H, CF::NH) / 32;
+          // stage dL/dz_l and the layer input, transposed, for the dW tiles
+          if (wave < CF::NTILE) {
+            if (has_tile) {
+              store_T<CF, OT>(sm.GZ(), gz, n0, lane);
+              if constexpr (l > 0) store_T<CF, CF::MTH>(sm.AT(), act[l - 1], n0, lane);
+            } else {
+              // empty tile: zero its columns
+              const int col = n0 + (lane & 31);
+              for (int rr = g; rr < 32 * OT; rr += 2) sm.GZ()[rr * CF::TS + col] = to_elem<CF>(0.0f);
+              if constexpr (l > 0)
+                for (int rr = g; rr < CF::H; rr += 2) sm.AT()[rr * CF::TS + col] = to_elem<CF>(0.0f);
+            }
+          }
+          if constexpr (l == 0) {
+            for (int e = tid; e < CF::WIN * CF::CI; e += kThreads) {
+              const int hh = e % CF::WIN, c = e / CF::WIN;
+              sm.AT()[c * CF::TS + hh] = sm.X()[hh * CF::XS + c];
+            }
+          }
+          __syncthreads();
+          // owned dW tiles of layer l: K = the window's hits
+          {
+            constexpr int MT = dw_mt(l, CF::H, CF::NH), NT = dw_nt(l, CF::H);
+            constexpr int T0 = dw_tile_off(l, CF::H, CF::NH);
+            constexpr int KSTEPS = CF::WIN / CF::KS;
+            static_for<MT * NT>([&](auto tc) {
+              constexpr int t = decltype(tc)::value;
+              constexpr int tau_i = T0 + t, mt = t / NT, nt = t % NT, slot = tau_i / kWaves;
+              if (tau_i % kWaves == wave) {
+                const typename CF::Elem* ga_ = sm.GZ() + (32 * mt + (lane & 31)) * CF::TS;
+                const typename CF::Elem* gb_ = sm.AT() + (32 * nt + (lane & 31)) * CF::TS;
+#pragma unroll
+                for (int s = 0; s < KSTEPS; ++s) {
+                  if constexpr (CF::BF) {
+                    const s16x8 av = *reinterpret_cast<const s16x8*>(ga_ + 16 * s + 8 * g);
+                    const s16x8 bv = *reinterpret_cast<const s16x8*>(gb_ + 16 * s + 8 * g);
+                    dw[slot] = mma(av, bv, dw[slot]);
+                  } else {
+                    dw[slot] = mma(ga_[2 * s + g], gb_[2 * s + g], dw[slot]);
+                  }
+                }
+              }
+            });
+          }
+          if (db_layer == l && db_row < out_real(l, CF::H, CF::NH)) {
+            const typename CF::Elem* gr_ = sm.GZ() + db_row * CF::TS;
+            float sacc = 0.0f;
+            for (int hh = 0; hh < CF::WIN; ++hh) {
+              if constexpr (CF::BF) sacc += bf16_f32(gr_[hh]);
+              else sacc += gr_[hh];
+            }
+            db += sacc;
+          }
+          // data gradient to the layer input
+          if (has_tile) {
+            if constexpr (l > 0) {
+              f32x16 ga[CF::MTH];
+              bwd_data<CF, l>(sm, gz, ga, lane);
+#pragma unroll
+              for (int mt = 0; mt < CF::MTH; ++mt) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) gz[mt][i] = act[l - 1][mt][i] > 0.0f ? ga[mt][i] : 0.0f;
+              }
+            } else {
+              bwd_data<CF, 0>(sm, gz, gx, lane);
+            }
+          }
+          __syncthreads();
+        });
+        // scatter dL/dx to the 8 corner features of each hit
+        if (has_tile && n0 + (lane & 31) < tw) {
+          const RecL rc = sm.rec()[n0 + (lane & 31)];
+          const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(rc.leaf));
+          const int4 c0 = lc[0], c1 = lc[1];
+          const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+          const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
+                      wz[2] = {1.0f - rc.uz, rc.uz};
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
+            float* gdst = sc.grad + static_cast<int64_t>(vid[j]) * CF::C;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (8 * q + 4 * g < CF::C) {
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                  unsafeAtomicAdd(gdst + 8 * q + 4 * g + p, wj * gx[0][4 * q + p]);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      s0 = s1;
+    }
+
+    if (live) {
+      if (CF::MODE != kBackward) {
+        if (a.rgb) {
+          a.rgb[3 * r] = cr;
+          a.rgb[3 * r + 1] = cg;
+          a.rgb[3 * r + 2] = cb;
+        }
+        if (a.depth) a.depth[r] = dep;
+        if (a.acc) a.acc[r] = acc;
+      }
+      if (CF::MODE == kTrain) {
+        const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
+                    eb = cb - a.t_rgb[3 * r + 2], ed = dep - a.t_depth[r];
+        loss_acc += a.loss_scale * ((er * er + eg * eg + eb * eb) * (1.0f / 3.0f) +
+                                    a.lambda_depth * fabsf(ed));
+      }
+    }
+  }
+
+  if constexpr (CF::BWD) {
+    // this block's partial sums of dL/dparams (every entry written once)
+    float* part = a.ws_partials + static_cast<int64_t>(blockIdx.x) * CF::NPARAMS;
+    static_for<CF::NL>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      constexpr int MT = dw_mt(l, CF::H, CF::NH), NT = dw_nt(l, CF::H);
+      constexpr int T0 = dw_tile_off(l, CF::H, CF::NH);
+      constexpr int IR = in_real(l, CF::C, CF::H), OR = out_real(l, CF::H, CF::NH);
+      static_for<MT * NT>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        constexpr int tau_i = T0 + t, mt = t / NT, nt = t % NT, slot = tau_i / kWaves;
+        if (tau_i % kWaves == wave) {
+          const int col = 32 * nt + (lane & 31);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int rowo = 32 * mt + drow(i, g);
+            if (rowo < OR && col < IR) part[par_w(l, CF::C, CF::H, CF::NH) + rowo * IR + col] = dw[slot][i];
+          }
+        }
+      });
+    });
+    if (db_layer >= 0) {
+      const int orl = db_layer == CF::NH ? 4 : CF::H;
+      if (db_row < orl) {
+        int pb = 0;
+        static_for<CF::NL>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          if (l == db_layer) pb = par_b(l, CF::C, CF::H, CF::NH);
+        });
+        part[pb + db_row] = db;
+      }
+    }
+    if (CF::MODE == kTrain) {
+      const float tot = block_sum(loss_acc, reinterpret_cast<float*>(sm.scr()));
+      if (tid == 0) a.ws_loss[blockIdx.x] = tot;
+    } else if (tid == 0) {
+      a.ws_loss[blockIdx.x] = 0.0f;
+    }
+  }
+}
+
+// Decoder alone on rows of X (diagnostics / tests): 128 rows per block pass.
+template <class CF>
+__global__ __launch_bounds__(kThreads) void k_mlp_rows(const float* __restrict__ params,
+                                                       const float* __restrict__ X, int64_t n,
+                                                       float* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  const Smem<CF> sm{smem_raw};
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
+  build_packs<CF>(sm, params);
+  __syncthreads();
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * CF::WIN; base < n;
+       base += static_cast<int64_t>(gridDim.x) * CF::WIN) {
+    for (int e = tid; e < CF::WIN * CF::CI; e += kThreads) {
+      const int hh = e / CF::CI, c = e % CF::CI;
+      const int64_t row = base + hh;
+      sm.X()[hh * CF::XS + c] = to_elem<CF>((row < n && c < CF::C) ? X[row * CF::C + c] : 0.0f);
+    }
+    __syncthreads();
+    f32x16 act[CF::NH][CF::MTH];
+    if (wave < CF::NTILE) {
+      const int n0 = 32 * wave;
+      const f32x16 o = mlp_tile<CF, false>(sm, n0, lane, act);
+      const int64_t row = base + n0 + (lane & 31);
+      if (g == 0 && row < n) {
+        out[4 * row] = o[0];
+        out[4 * row + 1] = o[1];
+        out[4 * row + 2] = o[2];
+        out[4 * row + 3] = o[3];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+
+int g_num_cus = 0;
+
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      g_num_cus = n;
+    else
+      g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+template <class CF>
+hipError_t run(const ShadeArgs& a, hipStream_t s, int* grid_used) {
+  const auto kern = k_shade<CF>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, CF::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  const int per_cu = (160 * 1024) / CF::LDS_BYTES;
+  int grid = num_cus() * (per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu));
+  if (grid > shade_grid_limit()) grid = shade_grid_limit();
+  if (grid > a.tab.n_blocks) grid = a.tab.n_blocks;
+  if (grid < 1) grid = 1;
+  *grid_used = grid;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), CF::LDS_BYTES, s, a);
+  return hipGetLastError();
+}
+
+template <int P, int C, int H, int NH>
+hipError_t run_mode(const ShadeArgs& a, int mode, hipStream_t s, int* grid) {
+  if (mode == kForward) return run<Cfg<P, C, H, NH, kForward>>(a, s, grid);
+  if (mode == kBackward) return run<Cfg<P, C, H, NH, kBackward>>(a, s, grid);
+  return run<Cfg<P, C, H, NH, kTrain>>(a, s, grid);
+}
+
+template <int P, int C, int H, int NH>
+hipError_t run_mlp(const float* params, const float* X, int64_t n, float* out, hipStream_t s) {
+  using CF = Cfg<P, C, H, NH, kForward>;
+  const auto kern = k_mlp_rows<CF>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, CF::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n + CF::WIN - 1) / CF::WIN;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), CF::LDS_BYTES, s,
+                     params, X, n, out);
+  return hipGetLastError();
+}
+
+// Supported decoder shapes (C, H, hidden layers).
+#define SVLF_SHAPES(X) X(8, 32, 2) X(16, 64, 3) X(32, 64, 3)
+
+}  // namespace
 
 int shade_grid_limit() { return 1024; }
 
-hipError_t launch_shade(const ShadeArgs&, int, hipStream_t, int* grid_used) {
+hipError_t launch_shade(const ShadeArgs& a, int mode, hipStream_t s, int* grid_used) {
   *grid_used = 0;
+  const int P = a.precision == SVLF_BF16 ? 1 : 0;
+#define SVLF_CASE(C_, H_, NH_)                                                         \
+  if (a.C == C_ && a.H == H_ && a.n_hidden == NH_)                                     \
+    return P ? run_mode<1, C_, H_, NH_>(a, mode, s, grid_used)                         \
+             : run_mode<0, C_, H_, NH_>(a, mode, s, grid_used);
+  SVLF_SHAPES(SVLF_CASE)
+#undef SVLF_CASE
   return hipErrorNotSupported;
 }
 
-hipError_t launch_mlp_forward(const float*, int, int, int, int, const float*, int64_t, float*,
-                              hipStream_t) {
+hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, int precision,
+                              const float* X, int64_t n, float* out, hipStream_t s) {
+  const int P = precision == SVLF_BF16 ? 1 : 0;
+#define SVLF_CASE(C_, H_, NH_)                                                         \
+  if (C == C_ && H == H_ && n_hidden == NH_)                                           \
+    return P ? run_mlp<1, C_, H_, NH_>(params, X, n, out, s)                           \
+             : run_mlp<0, C_, H_, NH_>(params, X, n, out, s);
+  SVLF_SHAPES(SVLF_CASE)
+#undef SVLF_CASE
   return hipErrorNotSupported;
 }
 

@@ -27,6 +27,8 @@ MAX_LAYERS = 8
 OK, E_INVAL, E_RANGE, E_WORKSPACE, E_UNSUPPORTED, E_HIP = 0, -1, -2, -3, -4, -5
 TAU_MODES = {"voxel": 0, "direct": 1, "world": 2}
 PRECISIONS = {"fp32": 0, "bf16": 1}
+FLAG_TRACE_ONLY = 1
+FLAG_REUSE_HITS = 2
 
 
 class Node(ct.Structure):
@@ -54,7 +56,7 @@ class Mlp(ct.Structure):
 
 class RenderOpts(ct.Structure):
     _fields_ = [("K", ct.c_int32), ("tau_mode", ct.c_int32), ("precision", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("flags", ct.c_int32)]
 
 
 _lib = None
@@ -169,12 +171,12 @@ def make_mlp(params, widths: Sequence[int]) -> Mlp:
     return m
 
 
-def make_opts(K, tau_mode="voxel", precision="fp32") -> RenderOpts:
+def make_opts(K, tau_mode="voxel", precision="fp32", flags=0) -> RenderOpts:
     o = RenderOpts()
     o.K = int(K)
     o.tau_mode = TAU_MODES[tau_mode] if isinstance(tau_mode, str) else int(tau_mode)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    o.reserved = 0
+    o.flags = int(flags)
     return o
 
 

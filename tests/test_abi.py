@@ -88,8 +88,9 @@ def test_render_validation(lib):
     assert args(sc, 17, offs, ct.byref(m), ct.byref(opts), None, 0) == svlf.E_RANGE
     bad = svlf.make_opts(0)
     assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_RANGE
-    bad = svlf.make_opts(4)
-    bad.reserved = 1
+    bad = svlf.make_opts(4, flags=8)
+    assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_INVAL
+    bad = svlf.make_opts(4, flags=svlf.FLAG_TRACE_ONLY | svlf.FLAG_REUSE_HITS)
     assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_INVAL
     bad = svlf.make_opts(4, precision=7)
     assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_RANGE

@@ -1,0 +1,259 @@
+"""GPU parity of the decoder, svlf_render, svlf_render_backward and
+svlf_train_step against the FP64 oracle (SVLF sections 4.1-4.3, Eq. 3)."""
+
+import numpy as np
+import pytest
+
+from oracle.render import bf16_round, loss as oracle_loss, mlp_forward as oracle_mlp, render_backward
+from synth.configs import get_config, tiny_workload, xavier_params
+from tests.gpu_cases import Case, assert_grad_close, assert_outputs_close, psnr
+from tests.helpers import random_rays
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 32, 32, 4), (16, 64, 64, 64, 4), (32, 64, 64, 64, 4)]
+
+
+@pytest.mark.parametrize("widths", SHAPES, ids=lambda w: "x".join(map(str, w)))
+@pytest.mark.parametrize("n", [1, 31, 300, 4099])
+def test_decoder_fp32(gpu_lib, widths, n):
+    import torch
+    rng = np.random.default_rng(n)
+    p = xavier_params(rng, widths)
+    p[-4:] = rng.normal(size=4).astype(np.float32)
+    X = rng.normal(0, 0.5, (n, widths[0])).astype(np.float32)
+    out = gpu_lib.mlp_forward(torch.from_numpy(p).cuda(), widths, gpu_lib.make_opts(4),
+                              torch.from_numpy(X).cuda()).cpu().numpy()
+    ref, _, _ = oracle_mlp(p.astype(np.float64), widths, X.astype(np.float64))
+    assert_outputs_close(out, ref, name="decoder fp32")
+
+
+@pytest.mark.parametrize("widths", SHAPES, ids=lambda w: "x".join(map(str, w)))
+def test_decoder_bf16(gpu_lib, widths):
+    import torch
+    rng = np.random.default_rng(5)
+    p = xavier_params(rng, widths)
+    X = rng.normal(0, 0.5, (2000, widths[0])).astype(np.float32)
+    out = gpu_lib.mlp_forward(torch.from_numpy(p).cuda(), widths, gpu_lib.make_opts(4, precision="bf16"),
+                              torch.from_numpy(X).cuda()).cpu().numpy()
+    ref, _, _ = oracle_mlp(p.astype(np.float64), widths, X.astype(np.float64), bf16=True)
+    err = np.abs(out - ref)
+    assert err.max() <= 2 ** -6 * np.abs(ref).max()
+    # most outputs agree to FP32-accumulation accuracy
+    assert np.mean(err <= 1e-5 * np.abs(ref).max()) > 0.5
+
+
+def _scene_cases(svlf):
+    yield "cfg0", Case.from_workload(svlf, get_config(0), feat_scale=4.0, sigma_bias=0.8)
+    w = tiny_workload(7, 5, 16, (16, 64, 64, 64, 4), 8, n_obj=3)
+    yield "tiny16", Case.from_workload(svlf, w, feat_scale=5.0, sigma_bias=1.0)
+    w = tiny_workload(8, 6, 32, (32, 64, 64, 64, 4), 8, n_obj=4)
+    yield "tiny32", Case.from_workload(svlf, w, feat_scale=5.0, sigma_bias=0.5)
+    w = tiny_workload(9, 4, 8, (8, 32, 32, 4), 3, kind="shell")
+    yield "shellK3", Case.from_workload(svlf, w, feat_scale=5.0, sigma_bias=2.0, tau_mode="world")
+
+
+def test_render_fp32_against_oracle(gpu_lib):
+    for name, case in _scene_cases(gpu_lib):
+        rng = np.random.default_rng(len(name))
+        o, d = random_rays(rng, 3001, inside_frac=0.2)
+        o[:3] = [[0.1, 0.2, 0.3], [-2, 0.1, 0.1], [np.inf, 0, 0]]
+        d[:3] = [[0, 0, 0], [1, np.nan, 0], [1, 0, 0]]
+        rgb, dep, acc = case.gpu_render(o, d)
+        er, ed, ea, st = case.oracle(o, d)
+        assert np.count_nonzero(st.ray_i) > 100, name
+        assert_outputs_close(rgb, er, 1.0, f"{name} rgb")
+        assert_outputs_close(acc, ea, 1.0, f"{name} acc")
+        assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), f"{name} depth")
+
+
+def test_render_modes_direct(gpu_lib):
+    w = tiny_workload(3, 4, 8, (8, 32, 32, 4), 6)
+    case = Case.from_workload(gpu_lib, w, feat_scale=3.0, sigma_bias=0.3, tau_mode="direct")
+    o, d = random_rays(np.random.default_rng(0), 1000)
+    rgb, dep, acc = case.gpu_render(o, d)
+    er, ed, ea, _ = case.oracle(o, d)
+    assert_outputs_close(rgb, er, 1.0, "direct rgb")
+    assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), "direct depth")
+
+
+def test_render_bf16_against_bf16_oracle(gpu_lib):
+    for name, case in _scene_cases(gpu_lib):
+        o, d = random_rays(np.random.default_rng(1), 2000)
+        rgb, dep, acc = case.gpu_render(o, d, "bf16")
+        br, bd, ba, _ = case.oracle(o, d, bf16=True)
+        er, ed, ea, _ = case.oracle(o, d)
+        S = max(1.0, np.abs(ed).max())
+        assert np.abs(rgb - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4, name
+        assert np.abs(dep - bd).max() <= 2 ** -6 * S + 1e-4 * S, name
+        assert np.abs(acc - ba).max() <= 2 ** -6 + 1e-4, name
+        assert psnr(rgb, er) > 35.0, (name, psnr(rgb, er))
+
+
+def test_workload1_full_view_sampled(gpu_lib):
+    """Full 800x800 view rendered in one call (the launch a bench would
+    time); 4096 seeded rays compared with the oracle."""
+    case = Case.from_workload(gpu_lib, get_config(1), feat_scale=3.0, sigma_bias=0.5)
+    o, d = get_config(1).view_rays()
+    rgb, dep, acc = case.gpu_render(o, d)
+    idx = np.random.default_rng(7).choice(o.shape[0], 4096, replace=False)
+    er, ed, ea, st = case.oracle(o[idx], d[idx])
+    assert_outputs_close(rgb[idx], er, 1.0, "cfg1 rgb")
+    assert_outputs_close(dep[idx], ed, max(1.0, np.abs(ed).max()), "cfg1 depth")
+    assert_outputs_close(acc[idx], ea, 1.0, "cfg1 acc")
+    assert np.all(acc >= 0) and np.all(acc <= 1 + 1e-6) and np.all(rgb <= acc[:, None] + 1e-6)
+
+
+def test_empty_scene(gpu_lib):
+    import torch
+    oc_ijk = np.zeros((0, 3), np.int32)
+    case = Case(gpu_lib, oc_ijk, 3, np.zeros((0, 8), np.float32),
+                xavier_params(np.random.default_rng(0), (8, 32, 32, 4)), (8, 32, 32, 4), 4)
+    o, d = random_rays(np.random.default_rng(0), 500)
+    rgb, dep, acc = case.gpu_render(o, d)
+    assert np.all(rgb == 0) and np.all(dep == 0) and np.all(acc == 0)
+
+
+def _gpu_backward(case, o, d, g_rgb, g_dep, g_acc, precision="fp32"):
+    import torch
+    to, td = case.rays(o, d)
+    gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+    gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    case.svlf.render_backward([case.scene], [o.shape[0]], case.params, case.widths,
+                              case.opts(precision), to, td, t(g_rgb), t(g_dep),
+                              None if g_acc is None else t(g_acc), [gF], gp)
+    torch.cuda.synchronize()
+    return gF.cpu().numpy(), gp.cpu().numpy()
+
+
+def test_backward_fp32_against_oracle(gpu_lib):
+    for name, case in _scene_cases(gpu_lib):
+        rng = np.random.default_rng(11)
+        o, d = random_rays(rng, 2500, inside_frac=0.2)
+        keep = case.smooth_rays(o, d)
+        o, d = o[keep], d[keep]
+        n = o.shape[0]
+        g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+        g_dep = rng.normal(size=n).astype(np.float32)
+        g_acc = rng.normal(size=n).astype(np.float32)
+        gF, gp = _gpu_backward(case, o, d, g_rgb, g_dep, g_acc)
+        _, _, _, st = case.oracle(o, d)
+        eF, ep = render_backward(st, g_rgb, g_dep, g_acc)
+        assert np.abs(eF).max() > 0 and np.abs(ep).max() > 0, name
+        assert_grad_close(gF, eF, f"{name} grad_features")
+        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+        # conservation: trilinear weights sum to one per hit
+        assert abs(gF.sum() - eF.sum()) <= 1e-4 * np.abs(eF).sum()
+
+
+def test_backward_accumulates(gpu_lib):
+    import torch
+    case = next(iter(_scene_cases(gpu_lib)))[1]
+    o, d = random_rays(np.random.default_rng(3), 700)
+    g = np.random.default_rng(4)
+    g_rgb = g.normal(size=(700, 3)).astype(np.float32)
+    g_dep = g.normal(size=700).astype(np.float32)
+    gF1, gp1 = _gpu_backward(case, o, d, g_rgb, g_dep, None)
+    to, td = case.rays(o, d)
+    gF = torch.from_numpy(gF1).cuda()
+    gp = torch.from_numpy(gp1).cuda()
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    case.svlf.render_backward([case.scene], [700], case.params, case.widths, case.opts(),
+                              to, td, t(g_rgb), t(g_dep), None, [gF], gp)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(gF.cpu().numpy(), 2 * gF1, rtol=1e-5, atol=1e-7 * np.abs(gF1).max())
+    np.testing.assert_allclose(gp.cpu().numpy(), 2 * gp1, rtol=1e-5, atol=1e-7 * np.abs(gp1).max())
+
+
+def test_train_step_fp32_against_oracle(gpu_lib):
+    import torch
+    for name, case in list(_scene_cases(gpu_lib))[:3]:
+        rng = np.random.default_rng(21)
+        o, d = random_rays(rng, 2000, inside_frac=0.0)
+        keep = case.smooth_rays(o, d)
+        o, d = o[keep], d[keep]
+        n = o.shape[0]
+        t_rgb = rng.uniform(0, 1, (n, 3)).astype(np.float32)
+        t_dep = rng.uniform(0, 5, n).astype(np.float32)
+        to, td = case.rays(o, d)
+        gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+        gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+        loss_t = torch.zeros(1, dtype=torch.float32, device="cuda")
+        out_rgb = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        out_dep = torch.empty((n,), dtype=torch.float32, device="cuda")
+        case.svlf.train_step([case.scene], [n], case.params, case.widths, case.opts(), to, td,
+                             torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_dep).cuda(),
+                             0.1, 1.0 / n, [gF], gp, out_rgb, out_dep, loss_t)
+        torch.cuda.synchronize()
+        er, ed, ea, st = case.oracle(o, d)
+        L, g_rgb, g_dep = oracle_loss(er, ed, t_rgb, t_dep, 0.1)
+        eF, ep = render_backward(st, g_rgb, g_dep)
+        assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L), name
+        assert_outputs_close(out_rgb.cpu().numpy(), er, 1.0, f"{name} rgb")
+        assert_grad_close(gF.cpu().numpy(), eF, f"{name} grad_features")
+        assert_grad_close(gp.cpu().numpy(), ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+
+
+def test_backward_bf16_against_bf16_oracle(gpu_lib):
+    for name, case in list(_scene_cases(gpu_lib))[:3]:
+        rng = np.random.default_rng(31)
+        o, d = random_rays(rng, 2000)
+        n = o.shape[0]
+        g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+        g_dep = rng.normal(size=n).astype(np.float32)
+        gF, gp = _gpu_backward(case, o, d, g_rgb, g_dep, None, "bf16")
+        _, _, _, st = case.oracle(o, d, bf16=True)
+        eF, ep = render_backward(st, g_rgb, g_dep)
+        assert np.abs(eF).max() > 0 and np.abs(gF).max() > 0, name
+        cos = lambda a, b: float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        assert cos(gF, eF) > 0.999, (name, cos(gF, eF))
+        assert cos(gp, ep) > 0.999, (name, cos(gp, ep))
+        assert np.linalg.norm(gF - eF) <= 0.05 * np.linalg.norm(eF)
+
+
+def test_multi_scene_render_and_backward(gpu_lib):
+    """Three scenes with different depths in one launch; each compared with
+    its own oracle run."""
+    import torch
+    cases, rays, counts = [], [], []
+    for i, (seed, depth) in enumerate([(40, 3), (41, 5), (42, 6)]):
+        w = tiny_workload(seed, depth, 16, (16, 64, 64, 64, 4), 8, n_obj=2)
+        sc = w.scene()
+        F = w.features() * 4.0
+        p = get_config(1).params().copy()
+        p[-1] = 0.7
+        cases.append(Case(gpu_lib, sc.leaf_ijk, sc.depth, F, p, w.widths, 8))
+        o_, d_ = random_rays(np.random.default_rng(seed), [1000, 257, 2049][i])
+        keep = cases[-1].smooth_rays(o_, d_)
+        rays.append((o_[keep], d_[keep]))
+        counts.append(int(keep.size))
+    o = np.concatenate([r[0] for r in rays])
+    d = np.concatenate([r[1] for r in rays])
+    to, td = cases[0].rays(o, d)
+    params = cases[0].params
+    rgb, dep, acc = gpu_lib.render([c.scene for c in cases], counts, params, cases[0].widths,
+                                   cases[0].opts(), to, td)
+    gFs = [torch.zeros(c.scene.features.shape, dtype=torch.float32, device="cuda") for c in cases]
+    gp = torch.zeros(params.shape, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(0)
+    g_rgb = rng.normal(size=(o.shape[0], 3)).astype(np.float32)
+    g_dep = rng.normal(size=o.shape[0]).astype(np.float32)
+    t = lambda x: torch.from_numpy(x).cuda()
+    gpu_lib.render_backward([c.scene for c in cases], counts, params, cases[0].widths,
+                            cases[0].opts(), to, td, t(g_rgb), t(g_dep), None, gFs, gp)
+    torch.cuda.synchronize()
+    rgb = rgb.cpu().numpy()
+    dep = dep.cpu().numpy()
+    ep_total = 0
+    start = 0
+    for c, n, gF in zip(cases, counts, gFs):
+        sl = slice(start, start + n)
+        er, ed, ea, st = c.oracle(o[sl], d[sl])
+        assert_outputs_close(rgb[sl], er, 1.0, "multi rgb")
+        assert_outputs_close(dep[sl], ed, max(1.0, np.abs(ed).max()), "multi depth")
+        eF, ep = render_backward(st, g_rgb[sl], g_dep[sl])
+        assert_grad_close(gF.cpu().numpy(), eF, "multi grad_features")
+        ep_total = ep_total + ep
+        start += n
+    assert_grad_close(gp.cpu().numpy(), ep_total, "multi grad_params", rel_nw=1e-4, rel_el=None)

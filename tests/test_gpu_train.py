@@ -1,0 +1,202 @@
+"""Training on the GPU with the library's own kernels (svlf_train_step +
+svlf_adam_step), and the autograd wrapper.
+
+The learned part must earn its keep: after training, held-out views rendered
+by the network beat (a) the untrained network and (b) the octree alone
+(depth = entry distance of the first occupied voxel, colour = mean training
+colour of hit pixels, black elsewhere) by at least 3 dB PSNR.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.render import render_backward
+from synth.configs import Workload, tiny_workload
+from tests.gpu_cases import Case, assert_grad_close, psnr
+from tests.helpers import random_rays
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def test_autograd_matches_render_backward(gpu_lib):
+    import torch
+    from paper_2205_07058_amd.autograd import render as ag_render
+    w = tiny_workload(7, 5, 16, (16, 64, 64, 64, 4), 8, n_obj=3)
+    case = Case.from_workload(gpu_lib, w, feat_scale=5.0, sigma_bias=1.0)
+    o, d = random_rays(np.random.default_rng(2), 1500)
+    keep = case.smooth_rays(o, d)
+    o, d = o[keep], d[keep]
+    feats = case.scene.features.clone().requires_grad_(True)
+    params = case.params.clone().requires_grad_(True)
+    to, td = case.rays(o, d)
+    rgb, dep, acc = ag_render(case.scene, params, case.widths, to, td, case.K, features=feats)
+    rng = np.random.default_rng(3)
+    wr = _t(rng.normal(size=(o.shape[0], 3)).astype(np.float32))
+    wd = _t(rng.normal(size=o.shape[0]).astype(np.float32))
+    wa = _t(rng.normal(size=o.shape[0]).astype(np.float32))
+    (rgb * wr).sum().add_((dep * wd).sum()).add_((acc * wa).sum()).backward()
+    _, _, _, st = case.oracle(o, d)
+    eF, ep = render_backward(st, wr.cpu().numpy(), wd.cpu().numpy(), wa.cpu().numpy())
+    assert_grad_close(feats.grad.cpu().numpy(), eF, "autograd features")
+    assert_grad_close(params.grad.cpu().numpy(), ep, "autograd params", rel_nw=1e-4, rel_el=None)
+    # directional finite difference of the FP32 GPU loss along the gradient
+    with torch.no_grad():
+        g = feats.grad / feats.grad.norm()
+        eps = 1e-2
+
+        def lossat(f):
+            r, dd, a = ag_render(case.scene, params, case.widths, to, td, case.K, features=f)
+            return float(((r * wr).sum() + (dd * wd).sum() + (a * wa).sum()).double())
+
+        fd = (lossat(feats + eps * g) - lossat(feats - eps * g)) / (2 * eps)
+        an = float((feats.grad * g).sum())
+        assert abs(fd - an) <= 2e-3 * abs(an), (fd, an)
+
+
+def test_adam_kernel(gpu_lib):
+    import torch
+    rng = np.random.default_rng(0)
+    n = 100003
+    p0 = rng.normal(size=n).astype(np.float32)
+    p = _t(p0.copy())
+    ref = torch.nn.Parameter(torch.from_numpy(p0.copy()).cuda())
+    opt = torch.optim.Adam([ref], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    bf = torch.empty(n, dtype=torch.int16, device="cuda")
+    for t in range(1, 6):
+        g = rng.normal(size=n).astype(np.float32)
+        gg = _t(g.copy())
+        gpu_lib.adam_step(p, gg, m, v, 1e-3, 0.9, 0.999, 1e-8, t, bf16_out=bf, zero_grad=True)
+        ref.grad = _t(g.copy())
+        opt.step()
+        assert float(gg.abs().max()) == 0.0
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(p.cpu().numpy(), ref.detach().cpu().numpy(), rtol=1e-6, atol=1e-7)
+    bits = bf.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    np.testing.assert_array_equal(bits.view(np.float32),
+                                  p.to(torch.bfloat16).float().cpu().numpy())
+
+
+def _train_setup(seed=5, image=48, n_views=16, n_held=4):
+    w = tiny_workload(seed, 6, 16, (16, 64, 64, 64, 4), 8, n_obj=3, image=image)
+    w.n_views, w.n_heldout = n_views, n_held
+    w.cam_radius = 3.5
+    return w
+
+
+def _octree_only_baseline(gpu_lib, w, case, train_rgb, held):
+    """Octree without the network: colour = mean training colour over hit
+    pixels, depth = first-hit entry distance; black / 0 where no hit."""
+    import torch
+    cols = []
+    sc = w.scene()
+    oc = gpu_lib.DeviceOctree(sc.leaf_ijk, sc.depth)
+    mean_col = train_rgb
+    out = []
+    for v in held:
+        o, d = w.view_rays(v)
+        leaf, tin, tout, cnt = gpu_lib.trace_hits(oc, _t(o), _t(d), 1)
+        hit = (cnt > 0).cpu().numpy()
+        rgb = np.where(hit[:, None], mean_col[None, :], 0.0)
+        out.append(rgb)
+    return out
+
+
+def _train(gpu_lib, w, precision, steps, batch, lr_f=1e-2, lr_p=1e-3, seed_feat=0):
+    import torch
+    from paper_2205_07058_amd.train import Trainer
+    sc = w.scene()
+    F = w.features()
+    p = w.params().copy()
+    scene = gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    params = _t(p)
+    tr = Trainer(scene, params, w.widths, w.K, precision=precision, lr_features=lr_f, lr_params=lr_p)
+    losses = []
+    for it in range(steps):
+        o, d, rgb, dep = w.train_batch(batch, step=it)
+        loss = tr.step(_t(o), _t(d), _t(rgb), _t(dep))
+        losses.append(float(loss.item()))
+    return tr, np.array(losses)
+
+
+def _eval(gpu_lib, w, tr, views):
+    import torch
+    ps = []
+    for v in views:
+        o, d = w.view_rays(v)
+        tgt, _ = w.targets(o, d)
+        rgb, dep, acc = tr.render(_t(o), _t(d))
+        torch.cuda.synchronize()
+        ps.append(psnr(rgb.cpu().numpy(), tgt))
+    return float(np.mean(ps))
+
+
+def test_training_beats_untrained_and_octree_only(gpu_lib):
+    import torch
+    w = _train_setup()
+    held = w.heldout_views()
+    from paper_2205_07058_amd.train import Trainer
+    # untrained network
+    sc = w.scene()
+    tr0 = Trainer(gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features()), _t(w.params().copy()),
+                  w.widths, w.K, precision="fp32")
+    p_untrained = _eval(gpu_lib, w, tr0, held)
+    tr, losses = _train(gpu_lib, w, "fp32", steps=300, batch=8192)
+    assert np.all(np.isfinite(losses))
+    assert losses[-20:].mean() < 0.5 * losses[:20].mean(), (losses[:5], losses[-5:])
+    p_trained = _eval(gpu_lib, w, tr, held)
+    # octree-only baseline
+    o, d, rgb, dep = w.train_batch(65536, step=10_000)
+    hit = np.any(rgb > 0, axis=1)
+    mean_col = rgb[hit].mean(axis=0) if hit.any() else np.zeros(3)
+    base = _octree_only_baseline(gpu_lib, w, None, mean_col, held)
+    p_base = float(np.mean([psnr(b, w.targets(*w.view_rays(v))[0]) for b, v in zip(base, held)]))
+    print(f"held-out PSNR: untrained {p_untrained:.2f} dB, octree-only {p_base:.2f} dB, trained {p_trained:.2f} dB")
+    assert p_trained >= p_untrained + 3.0
+    assert p_trained >= p_base + 3.0
+
+
+def test_bf16_training_close_to_fp32(gpu_lib):
+    w = _train_setup(seed=6)
+    held = w.heldout_views()
+    tr32, l32 = _train(gpu_lib, w, "fp32", steps=250, batch=8192)
+    tr16, l16 = _train(gpu_lib, w, "bf16", steps=250, batch=8192)
+    p32 = _eval(gpu_lib, w, tr32, held)
+    p16 = _eval(gpu_lib, w, tr16, held)
+    print(f"held-out PSNR after 250 steps: fp32 {p32:.3f} dB, bf16 {p16:.3f} dB")
+    assert p16 >= p32 - 0.3, (p16, p32)
+
+
+def test_checkpoint_resume(gpu_lib):
+    import torch
+    from paper_2205_07058_amd.train import Trainer
+    w = _train_setup(seed=7)
+    sc = w.scene()
+
+    def fresh():
+        return Trainer(gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features()),
+                       _t(w.params().copy()), w.widths, w.K, precision="bf16", lr_features=1e-2)
+
+    batches = [w.train_batch(4096, step=i) for i in range(20)]
+    a = fresh()
+    for o, d, rgb, dep in batches:
+        a.step(_t(o), _t(d), _t(rgb), _t(dep))
+    b = fresh()
+    for o, d, rgb, dep in batches[:10]:
+        b.step(_t(o), _t(d), _t(rgb), _t(dep))
+    sd = {k: (v.cpu() if torch.is_tensor(v) else v) for k, v in b.state_dict().items()}
+    c = fresh()
+    c.load_state_dict({k: (v.cuda() if torch.is_tensor(v) else v) for k, v in sd.items()})
+    for o, d, rgb, dep in batches[10:]:
+        c.step(_t(o), _t(d), _t(rgb), _t(dep))
+    torch.cuda.synchronize()
+    # FP32 atomics make runs differ in the last bits only
+    np.testing.assert_allclose(c.params.cpu().numpy(), a.params.cpu().numpy(), rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(c.scene.features.cpu().numpy(), a.scene.features.cpu().numpy(),
+                               rtol=1e-3, atol=1e-5)
