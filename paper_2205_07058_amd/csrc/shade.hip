@@ -154,6 +154,7 @@ struct Cfg {
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+  static_assert(!BWD || WIN * C * 4 <= 2 * TROWS * TS * EB, "dL/dx staging fits in GZ + AT");
 };
 
 // Hit record in LDS (32 bytes).
@@ -180,18 +181,23 @@ __device__ __forceinline__ int kmap_x(int s, int g, int j) {
   return 4 * (2 * (s >> 2) + g) + (s & 3);
 }
 
+// Dynamic LDS of the shading kernels.  Every LDS address is derived from
+// this array directly, so the compiler keeps LDS accesses as ds_* operations
+// (an LDS pointer stored in an object would be accessed as a generic address,
+// and each generic access waits for all outstanding global memory traffic).
+extern __shared__ __attribute__((aligned(16))) char g_smem[];
+
 template <class CF>
 struct Smem {
-  char* base;
-  __device__ typename CF::Elem* fpack() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_FP); }
-  __device__ typename CF::Elem* bpack() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_BP); }
-  __device__ float* bias() const { return reinterpret_cast<float*>(base + CF::L_BI); }
-  __device__ RecL* rec() const { return reinterpret_cast<RecL*>(base + CF::L_REC); }
-  __device__ typename CF::Elem* X() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_X); }
-  __device__ float* out() const { return reinterpret_cast<float*>(base + CF::L_OUT); }
-  __device__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_GZ); }
-  __device__ typename CF::Elem* AT() const { return reinterpret_cast<typename CF::Elem*>(base + CF::L_AT); }
-  __device__ int* scr() const { return reinterpret_cast<int*>(base + CF::L_SCR); }
+  __device__ __forceinline__ typename CF::Elem* fpack() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_FP); }
+  __device__ __forceinline__ typename CF::Elem* bpack() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_BP); }
+  __device__ __forceinline__ float* bias() const { return reinterpret_cast<float*>(g_smem + CF::L_BI); }
+  __device__ __forceinline__ RecL* rec() const { return reinterpret_cast<RecL*>(g_smem + CF::L_REC); }
+  __device__ __forceinline__ typename CF::Elem* X() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_X); }
+  __device__ __forceinline__ float* out() const { return reinterpret_cast<float*>(g_smem + CF::L_OUT); }
+  __device__ __forceinline__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_GZ); }
+  __device__ __forceinline__ typename CF::Elem* AT() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_AT); }
+  __device__ __forceinline__ int* scr() const { return reinterpret_cast<int*>(g_smem + CF::L_SCR); }
 };
 
 template <class CF>
@@ -203,7 +209,7 @@ __device__ __forceinline__ typename CF::Elem to_elem(float v) {
 // ------------------------------------------------------------ weight packs
 
 template <class CF>
-__device__ void build_packs(const Smem<CF>& sm, const float* __restrict__ params) {
+__device__ __forceinline__ void build_packs(const Smem<CF>& sm, const float* __restrict__ params) {
   constexpr int E = CF::BF ? 8 : 1;
   static_for<CF::NL>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
@@ -411,8 +417,7 @@ __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf
 
 template <class CF>
 __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-  const Smem<CF> sm{smem_raw};
+  const Smem<CF> sm{};
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
 
   build_packs<CF>(sm, a.params);
@@ -430,16 +435,17 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
   }
   float loss_acc = 0.0f;
 
-  // XCD-aware item ranges: blocks of one XCD get neighbouring ray blocks
+  // Items (256-ray blocks) are dealt round-robin over the persistent grid
+  // for balance; the logical block index groups the blocks of one XCD
+  // (hardware places block b on XCD b % 8) so that each XCD works on
+  // neighbouring rays in every round and shares their features in its L2.
   const int G = gridDim.x, b = blockIdx.x;
   const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   const int NB = a.tab.n_blocks;
-  const int per = (NB + G - 1) / G;
-  const int it_begin = lb * per, it_end = min(NB, (lb + 1) * per);
 
   __syncthreads();
 
-  for (int item = it_begin; item < it_end; ++item) {
+  for (int item = lb; item < NB; item += G) {
     int si = 0;
     while (si + 1 < a.tab.n && item >= a.tab.s[si + 1].block_begin) ++si;
     const DevScene& sc = a.tab.s[si];
@@ -708,24 +714,40 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           }
           __syncthreads();
         });
-        // scatter dL/dx to the 8 corner features of each hit
-        if (has_tile && n0 + (lane & 31) < tw) {
-          const RecL rc = sm.rec()[n0 + (lane & 31)];
-          const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(rc.leaf));
-          const int4 c0 = lc[0], c1 = lc[1];
-          const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-          const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
-                      wz[2] = {1.0f - rc.uz, rc.uz};
+        // scatter dL/dx to the 8 corner features of each hit.  dL/dx is
+        // staged through LDS so that the lanes of one atomic instruction
+        // cover whole contiguous feature rows (lane = channel): the memory
+        // system then merges them per cache line instead of issuing one
+        // transaction per lane.
+        float* gxs = reinterpret_cast<float*>(sm.GZ());      // [WIN][C] FP32
+        if (has_tile) {
+          const int row = n0 + (lane & 31);
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
-            float* gdst = sc.grad + static_cast<int64_t>(vid[j]) * CF::C;
+          for (int q = 0; q < 4; ++q) {
+            if (8 * q + 4 * g < CF::C) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (8 * q + 4 * g < CF::C) {
+              for (int p = 0; p < 4; ++p) gxs[row * CF::C + 8 * q + 4 * g + p] = gx[0][4 * q + p];
+            }
+          }
+        }
+        __syncthreads();
+        if (has_tile) {
+          constexpr int HPI = 64 / CF::C;            // hits per instruction
+          const int c = lane % CF::C, hs = lane / CF::C;
+          for (int k = 0; k < 32; k += HPI) {
+            const int hh = n0 + k + hs;
+            if (hh < tw) {
+              const RecL rc = sm.rec()[hh];
+              const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(rc.leaf));
+              const int4 c0 = lc[0], c1 = lc[1];
+              const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+              const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
+                          wz[2] = {1.0f - rc.uz, rc.uz};
+              const float gv = gxs[hh * CF::C + c];
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
-                  unsafeAtomicAdd(gdst + 8 * q + 4 * g + p, wj * gx[0][4 * q + p]);
+              for (int j = 0; j < 8; ++j) {
+                const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
+                unsafeAtomicAdd(sc.grad + static_cast<int64_t>(vid[j]) * CF::C + c, wj * gv);
               }
             }
           }
@@ -800,8 +822,7 @@ template <class CF>
 __global__ __launch_bounds__(kThreads) void k_mlp_rows(const float* __restrict__ params,
                                                        const float* __restrict__ X, int64_t n,
                                                        float* __restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-  const Smem<CF> sm{smem_raw};
+  const Smem<CF> sm{};
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
   build_packs<CF>(sm, params);
   __syncthreads();
