@@ -49,7 +49,8 @@ def parse():
                     help="rays of the batch the oracle trains on for the CPU baseline")
     ap.add_argument("--psnr-rays", type=int, default=16384)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr")
+                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,copy,"
+                         "multi (the ragged 8-scene workload; not in 'all')")
     return ap.parse_args()
 
 
@@ -158,6 +159,19 @@ def main():
         scene.features.copy_(T(F))
         scene.refresh_bf16()
 
+    if "copy" in sections:
+        # a plain device copy of known size: calibrates the HBM byte counters
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        ms, _ = timer.run(lambda: dst.copy_(src), args.steps, args.warmup)
+        res["copy_gbs"] = 2 * src.numel() * 4 / (ms / args.steps * 1e-3) / 1e9
+        log(f"device copy of 1 GiB: {ms / args.steps:.3f} ms ({res['copy_gbs']:.0f} GB/s read+write)")
+        del src, dst
+
+    multi = None
+    if "multi" in sections:
+        multi = bench_multi(torch, svlf, timer, args)
+
     stages = {}
     if "stages" in sections:
         # split one BF16 train step into its kernels with events between them
@@ -243,11 +257,73 @@ def main():
         if "adam_ms" in res and ms else None,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
         "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
+        "device_copy_gbs": round(res["copy_gbs"], 1) if "copy_gbs" in res else None,
+        "multi_scene": multi,
         "roofline": roof,
         "cpu_baseline": cpu,
         "paper_context": "SVLF renders 0.08 s/frame on one RTX 3090 and trains 30K steps in 2.7 h on one V100 (Table 6)",
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_multi(torch, svlf, timer, args):
+    """Ragged workload: 8 scenes (depths 7..10, 0.5-3% occupancy) sharing one
+    BF16 decoder, 2^16..2^20 rays each, rendered and trained in one launch of
+    each kernel; also captured once in a HIP graph and replayed.  Features
+    are drawn on the device from a seeded generator."""
+    from synth.configs import get_multi
+    m = get_multi()
+    counts = m.ray_counts()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    scenes, os_, ds_ = [], [], []
+    t0 = time.time()
+    leaves = []
+    for i in range(len(m.depths)):
+        sc = m.scene(i)
+        oc = svlf.DeviceOctree(sc.leaf_ijk, sc.depth)
+        feats = torch.randn((sc.n_vertices, m.C), generator=gen, device="cuda") * 0.1
+        ds = svlf.DeviceScene(oc, feats)
+        ds.refresh_bf16()
+        scenes.append(ds)
+        leaves.append(int(sc.leaf_ijk.shape[0]))
+        o, d = m.rays(i, counts[i])
+        os_.append(o)
+        ds_.append(d)
+        log(f"multi scene {i}: depth {m.depths[i]}, {leaves[-1]} leaves, {counts[i]} rays ({time.time() - t0:.1f}s)")
+    n = sum(counts)
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    o_t, d_t = T(np.concatenate(os_)), T(np.concatenate(ds_))
+    params = torch.from_numpy(m.params()).cuda()
+    opts = svlf.make_opts(m.K, "voxel", "bf16")
+    ws = svlf.Workspace()
+    out = (torch.empty((n, 3), device="cuda"), torch.empty(n, device="cuda"), torch.empty(n, device="cuda"))
+    rng = np.random.default_rng(5)
+    t_rgb, t_dep = T(rng.uniform(0, 1, (n, 3)).astype(np.float32)), T(rng.uniform(0, 6, n).astype(np.float32))
+    gFs = [torch.zeros_like(s.features) for s in scenes]
+    gp = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    fwd = lambda: svlf.render(scenes, counts, params, m.widths, opts, o_t, d_t, *out, workspace=ws)
+    trn = lambda: svlf.train_step(scenes, counts, params, m.widths, opts, o_t, d_t, t_rgb, t_dep, 0.1,
+                                  1.0 / n, gFs, gp, loss_out=loss, workspace=ws)
+    ms_f, _ = timer.run(fwd, args.steps, args.warmup)
+    ms_t, _ = timer.run(trn, args.steps, args.warmup)
+    graph = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(graph, stream=st):
+            trn()
+    torch.cuda.current_stream().wait_stream(st)
+    ms_g, _ = timer.run(graph.replay, args.steps, args.warmup)
+    res = {"workload": "8 scenes, depths " + ",".join(map(str, m.depths)) + ", C=32, MLP 32-64-64-64-4, K=8",
+           "leaves": leaves, "rays": counts, "total_rays": n,
+           "fwd_bf16_rays_per_s": round(n / (ms_f / args.steps * 1e-3), 1),
+           "train_bf16_rays_per_s": round(n / (ms_t / args.steps * 1e-3), 1),
+           "train_bf16_graph_replay_rays_per_s": round(n / (ms_g / args.steps * 1e-3), 1)}
+    log(f"multi: fwd {res['fwd_bf16_rays_per_s'] / 1e6:.1f} M rays/s, train {res['train_bf16_rays_per_s'] / 1e6:.1f} "
+        f"M rays/s, graph replay {res['train_bf16_graph_replay_rays_per_s'] / 1e6:.1f} M rays/s")
+    return res
 
 
 def cpu_baseline(w, sc, F, p, ob, db, rgb_t, dep_t, n_rays, oc=None):

@@ -146,7 +146,7 @@ struct Cfg {
   static constexpr int L_BP = align16(L_FP + FWD_ELEMS * EB);
   static constexpr int L_BI = align16(L_BP + BWD_ELEMS * EB);
   static constexpr int L_REC = align16(L_BI + BIAS_ELEMS * 4);
-  static constexpr int L_X = align16(L_REC + WIN * 32);
+  static constexpr int L_X = align16(L_REC + WIN * 64);
   static constexpr int L_OUT = align16(L_X + WIN * XS * EB);
   static constexpr int L_GZ = align16(L_OUT + WIN * 16);
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
@@ -157,7 +157,9 @@ struct Cfg {
   static_assert(!BWD || WIN * C * 4 <= 2 * TROWS * TS * EB, "dL/dx staging fits in GZ + AT");
 };
 
-// Hit record in LDS (32 bytes).
+// Hit record in LDS (64 bytes): the leaf's corner vertex ids are fetched
+// once by the ray's lane, so the gather and the gradient scatter start with
+// independent feature-row accesses.
 struct RecL {
   int32_t leaf;
   float ux, uy, uz;
@@ -165,6 +167,7 @@ struct RecL {
   float dt;
   float T;
   float pad;
+  int4 v0, v1;
 };
 
 // K index of step s, lane group g, element j for an operand that comes from
@@ -292,12 +295,39 @@ __device__ __forceinline__ void relu16(f32x16& t) {
   for (int i = 0; i < 16; ++i) t[i] = t[i] > 0.0f ? t[i] : 0.0f;
 }
 
+// Kept hidden activations of a 32x32 tile (backward only): FP32 values, or
+// on the BF16 path the bfloat16 values the MFMA operands were made of.
+template <bool BF>
+struct ActTile;
+template <>
+struct ActTile<true> {
+  s16x8 lo, hi;
+  __device__ __forceinline__ void set(const f32x16& t) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      lo[j] = bf16_rne(t[j]);
+      hi[j] = bf16_rne(t[8 + j]);
+    }
+  }
+  __device__ __forceinline__ bool positive(int i) const { return (i < 8 ? lo[i] : hi[i - 8]) > 0; }
+  __device__ __forceinline__ uint16_t elem(int i) const {
+    return static_cast<uint16_t>(i < 8 ? lo[i] : hi[i - 8]);
+  }
+};
+template <>
+struct ActTile<false> {
+  f32x16 v;
+  __device__ __forceinline__ void set(const f32x16& t) { v = t; }
+  __device__ __forceinline__ bool positive(int i) const { return v[i] > 0.0f; }
+  __device__ __forceinline__ float elem(int i) const { return v[i]; }
+};
+
 // Decoder forward on the 32 hits [n0, n0+32) of the window.  Returns the
 // output tile (rows 0..3 = raw o_0..o_3 in registers 0..3 of lanes 0..31);
 // with SAVE, the post-ReLU activations of every hidden layer are kept.
 template <class CF, bool SAVE>
 __device__ __forceinline__ f32x16 mlp_tile(const Smem<CF>& sm, int n0, int lane,
-                                           f32x16 (&act)[CF::NH][CF::MTH]) {
+                                           ActTile<CF::BF> (&act)[CF::NH][CF::MTH]) {
   const int g = lane >> 5, row = n0 + (lane & 31);
   f32x16 cur[CF::MTH];
   {
@@ -315,7 +345,7 @@ __device__ __forceinline__ f32x16 mlp_tile(const Smem<CF>& sm, int n0, int lane,
     for (int mt = 0; mt < CF::MTH; ++mt) relu16(cur[mt]);
     if constexpr (SAVE) {
 #pragma unroll
-      for (int mt = 0; mt < CF::MTH; ++mt) act[0][mt] = cur[mt];
+      for (int mt = 0; mt < CF::MTH; ++mt) act[0][mt].set(cur[mt]);
     }
   }
   static_for<CF::NH - 1>([&](auto lc) {
@@ -335,7 +365,7 @@ __device__ __forceinline__ f32x16 mlp_tile(const Smem<CF>& sm, int n0, int lane,
     for (int mt = 0; mt < CF::MTH; ++mt) {
       relu16(nxt[mt]);
       cur[mt] = nxt[mt];
-      if constexpr (SAVE) act[l][mt] = nxt[mt];
+      if constexpr (SAVE) act[l][mt].set(nxt[mt]);
     }
   });
   constexpr int S = CF::H / CF::KS;
@@ -360,6 +390,18 @@ __device__ __forceinline__ void bwd_data(const Smem<CF>& sm, const f32x16* gt, f
     const typename CF::Op b = d_operand<CF>(gt, s);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) r[mt] = mma(pack_operand<CF>(B, mt, s, S, lane), b, r[mt]);
+  }
+}
+
+// Writes kept activation tiles of the hits [n0, n0+32) transposed into T.
+template <class CF, int NT>
+__device__ __forceinline__ void store_act_T(typename CF::Elem* T, const ActTile<CF::BF>* t, int n0,
+                                            int lane) {
+  const int g = lane >> 5, col = n0 + (lane & 31);
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) T[(32 * mt + drow(i, g)) * CF::TS + col] = t[mt].elem(i);
   }
 }
 
@@ -478,6 +520,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
         const HitRec* hr = a.hits + r * a.K;
         for (int q = 0; q < count; ++q) {
           const HitRec hh = hr[q];
+          const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hh.leaf));
           const float tm = 0.5f * (hh.tin + hh.tout);
           const float lx = -1.0f + static_cast<float>(hh.ijk & 1023u) * h;
           const float ly = -1.0f + static_cast<float>((hh.ijk >> 10) & 1023u) * h;
@@ -491,6 +534,8 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           rc.dt = hh.tout - hh.tin;
           rc.T = 0.0f;
           rc.pad = 0.0f;
+          rc.v0 = lc[0];
+          rc.v1 = lc[1];
           sm.rec()[off - s0 + q] = rc;
         }
       }
@@ -511,9 +556,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           for (int i = 0; i < VPT; ++i) v[i] = 0.0f;
           if (hh < tw) {
             const RecL rc = sm.rec()[hh];
-            const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(rc.leaf));
-            const int4 c0 = lc[0], c1 = lc[1];
-            const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            const int vid[8] = {rc.v0.x, rc.v0.y, rc.v0.z, rc.v0.w, rc.v1.x, rc.v1.y, rc.v1.z, rc.v1.w};
             const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
                         wz[2] = {1.0f - rc.uz, rc.uz};
 #pragma unroll
@@ -548,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
       __syncthreads();
 
       // decoder on the window: one 32-hit tile per wave
-      f32x16 act[CF::NH][CF::MTH];
+      ActTile<CF::BF> act[CF::NH][CF::MTH];
       const int n0 = 32 * wave;
       const bool has_tile = wave < CF::NTILE && n0 < tw;
       if (has_tile) {
@@ -649,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           if (wave < CF::NTILE) {
             if (has_tile) {
               store_T<CF, OT>(sm.GZ(), gz, n0, lane);
-              if constexpr (l > 0) store_T<CF, CF::MTH>(sm.AT(), act[l - 1], n0, lane);
+              if constexpr (l > 0) store_act_T<CF, CF::MTH>(sm.AT(), act[l - 1], n0, lane);
             } else {
               // empty tile: zero its columns
               const int col = n0 + (lane & 31);
@@ -692,9 +735,16 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           if (db_layer == l && db_row < out_real(l, CF::H, CF::NH)) {
             const typename CF::Elem* gr_ = sm.GZ() + db_row * CF::TS;
             float sacc = 0.0f;
-            for (int hh = 0; hh < CF::WIN; ++hh) {
-              if constexpr (CF::BF) sacc += bf16_f32(gr_[hh]);
-              else sacc += gr_[hh];
+            if constexpr (CF::BF) {
+#pragma unroll 4
+              for (int hh = 0; hh < CF::WIN; hh += 8) {
+                const s16x8 v = *reinterpret_cast<const s16x8*>(gr_ + hh);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sacc += bf16_f32(static_cast<uint16_t>(v[j]));
+              }
+            } else {
+#pragma unroll 8
+              for (int hh = 0; hh < CF::WIN; ++hh) sacc += gr_[hh];
             }
             db += sacc;
           }
@@ -706,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
 #pragma unroll
               for (int mt = 0; mt < CF::MTH; ++mt) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) gz[mt][i] = act[l - 1][mt][i] > 0.0f ? ga[mt][i] : 0.0f;
+                for (int i = 0; i < 16; ++i) gz[mt][i] = act[l - 1][mt].positive(i) ? ga[mt][i] : 0.0f;
               }
             } else {
               bwd_data<CF, 0>(sm, gz, gx, lane);
@@ -738,9 +788,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
             const int hh = n0 + k + hs;
             if (hh < tw) {
               const RecL rc = sm.rec()[hh];
-              const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(rc.leaf));
-              const int4 c0 = lc[0], c1 = lc[1];
-              const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+              const int vid[8] = {rc.v0.x, rc.v0.y, rc.v0.z, rc.v0.w, rc.v1.x, rc.v1.y, rc.v1.z, rc.v1.w};
               const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
                           wz[2] = {1.0f - rc.uz, rc.uz};
               const float gv = gxs[hh * CF::C + c];
@@ -834,7 +882,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const float* __restrict__
       sm.X()[hh * CF::XS + c] = to_elem<CF>((row < n && c < CF::C) ? X[row * CF::C + c] : 0.0f);
     }
     __syncthreads();
-    f32x16 act[CF::NH][CF::MTH];
+    ActTile<CF::BF> act[CF::NH][CF::MTH];
     if (wave < CF::NTILE) {
       const int n0 = 32 * wave;
       const f32x16 o = mlp_tile<CF, false>(sm, n0, lane, act);

@@ -233,7 +233,68 @@ def _make(i, seed=None):
     raise KeyError(i)
 
 
-CONFIGS = (0, 1, 2, 3)
+CONFIGS = (0, 1, 2, 3, 4)
+
+# Workload 4: ragged batch of scenes sharing one decoder (C = 32, MLP
+# 32-64-64-64-4, K = 8).  Depths as specified; occupied fractions are fixed
+# points of the stated 0.5-3% range (largest at the coarsest depth, so no
+# scene exceeds ~6M leaves); ray counts are seeded log-uniform in
+# [2^16, 2^20] per scene.
+MULTI_DEPTHS = (7, 8, 8, 9, 9, 10, 10, 10)
+MULTI_FRACTIONS = (0.03, 0.02, 0.015, 0.01, 0.008, 0.006, 0.005, 0.005)
+
+
+@dataclasses.dataclass
+class MultiScene:
+    seed: int
+    depths: tuple
+    fractions: tuple
+    C: int = 32
+    widths: tuple = (32, 64, 64, 64, 4)
+    K: int = 8
+    n_ell: int = 12
+    n_box: int = 6
+    ray_lo: int = 1 << 16
+    ray_hi: int = 1 << 20
+
+    def ray_counts(self):
+        rng = streams(self.seed)["batch"]
+        lg = rng.uniform(np.log2(self.ray_lo), np.log2(self.ray_hi), len(self.depths))
+        return [int(2 ** x) for x in lg]
+
+    def scene(self, i):
+        sc, _ = calibrated_surface_scene(self.seed * 100 + i, self.depths[i], self.n_ell,
+                                         self.n_box, self.fractions[i])
+        return sc
+
+    def params(self):
+        return xavier_params(streams(self.seed)["mlp"], self.widths)
+
+    def rays(self, i, n):
+        """n rays of scene i from cameras on a sphere of radius 4 (one random
+        camera per ray, random pixel of a 1600^2 view)."""
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([self.seed, 77, i])))
+        v = rng.standard_normal((n, 3))
+        pos = 4.0 * v / np.linalg.norm(v, axis=1, keepdims=True)
+        f = -pos / np.linalg.norm(pos, axis=1, keepdims=True)
+        up = np.where(np.abs(f[:, 2:3]) > 0.999, [[0.0, 1.0, 0.0]], [[0.0, 0.0, 1.0]])
+        r = np.cross(f, up)
+        r /= np.linalg.norm(r, axis=1, keepdims=True)
+        u = np.cross(r, f)
+        t = np.tan(np.deg2rad(25.0))
+        px = rng.uniform(-1, 1, (n, 1)) * t
+        py = rng.uniform(-1, 1, (n, 1)) * t
+        d = f + px * r + py * u
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        return pos.astype(np.float32), d.astype(np.float32)
+
+
+def get_multi(seed=4, small=False) -> MultiScene:
+    if small:
+        # the same structure at test scale (depths 3..6, 2^8..2^12 rays)
+        return MultiScene(seed, (3, 4, 4, 5, 5, 6, 6, 6), MULTI_FRACTIONS, n_ell=4, n_box=2,
+                          ray_lo=1 << 8, ray_hi=1 << 12)
+    return MultiScene(seed, MULTI_DEPTHS, MULTI_FRACTIONS)
 
 
 def get_config(i, seed=None) -> Workload:
