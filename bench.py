@@ -34,6 +34,19 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the BF16 train shading kernel on this workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 1 GiB device copy
+# (profiles/shade_train_bf16_paper_scale.md).  Valid only for the kernel
+# source they were taken with; reported as null once shade.hip changes.
+MEASURED_TRAFFIC = {"shade_src_sha256_prefix": "082eacc453c55d46", "bytes": 2 * 428999 * 1024 + 1424028 * 1024}
+
+
+def shade_source_prefix():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2205_07058_amd", "csrc", "shade.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -222,8 +235,11 @@ def main():
     if stages:
         sh_ms = stages["shade_reduce_ms"]
         achieved = bytes_launch / (sh_ms * 1e-3) / 1e9
+        traffic = (MEASURED_TRAFFIC["bytes"] if shade_source_prefix() == MEASURED_TRAFFIC["shade_src_sha256_prefix"]
+                   else None)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                 "kernel": "k_shade<bf16,32,64,3,train> + k_reduce",
                 "bytes_per_launch": int(bytes_launch),
                 "bytes_per_hit": bytes_hit, "bytes_per_ray": bytes_ray, "hits_per_ray": round(hits_b / n_b, 4)}
