@@ -145,8 +145,9 @@ int make_table(const svlf_scene* scenes, int n_scenes, const int64_t* offs, bool
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace: [hit slots n*K][counts n][per-block dW partials][per-block loss]
+// [ray-refill counter of the traversal]
 struct WsLayout {
-  size_t hits, cnt, partials, loss, total;
+  size_t hits, cnt, partials, loss, counter, total;
 };
 
 WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
@@ -160,6 +161,8 @@ WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
   off = align256(off + static_cast<size_t>(shade_grid_limit()) * n_params * sizeof(float));
   w.loss = off;
   off = align256(off + static_cast<size_t>(shade_grid_limit()) * sizeof(float));
+  w.counter = off;
+  off = align256(off + sizeof(unsigned long long));
   w.total = off;
   return w;
 }
@@ -204,7 +207,8 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   hipError_t e = hipSuccess;
   if (!(opts->flags & SVLF_FLAG_REUSE_HITS)) {
     e = launch_trace_internal(a.tab, ray_o, ray_d, opts->K, const_cast<HitRec*>(a.hits),
-                              const_cast<int32_t*>(a.cnt), s);
+                              const_cast<int32_t*>(a.cnt),
+                              reinterpret_cast<unsigned long long*>(base + w.counter), s);
     if (e != hipSuccess) return hip_fail(e, who);
   }
   if (opts->flags & SVLF_FLAG_TRACE_ONLY) return SVLF_OK;

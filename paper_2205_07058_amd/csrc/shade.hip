@@ -150,7 +150,8 @@ struct Cfg {
   static constexpr int L_OUT = align16(L_X + WIN * XS * EB);
   static constexpr int L_GZ = align16(L_OUT + WIN * 16);
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
-  static constexpr int L_SCR = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
+  static constexpr int L_MAP = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
+  static constexpr int L_SCR = align16(L_MAP + WIN * 4);
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
@@ -201,6 +202,7 @@ struct Smem {
   __device__ __forceinline__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_GZ); }
   __device__ __forceinline__ typename CF::Elem* AT() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_AT); }
   __device__ __forceinline__ int* scr() const { return reinterpret_cast<int*>(g_smem + CF::L_SCR); }
+  __device__ __forceinline__ int* hmap() const { return reinterpret_cast<int*>(g_smem + CF::L_MAP); }
 };
 
 template <class CF>
@@ -496,11 +498,6 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
     const int count = live ? a.cnt[r] : 0;
     const float h = __int_as_float((128 - sc.depth) << 23);       // 2^(1-depth)
     const float inv_h = __int_as_float((126 + sc.depth) << 23);   // 2^(depth-1)
-    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0;
-    if (live && count > 0) {
-      ox = a.o[3 * r]; oy = a.o[3 * r + 1]; oz = a.o[3 * r + 2];
-      dx = a.d[3 * r]; dy = a.d[3 * r + 1]; dz = a.d[3 * r + 2];
-    }
     int total;
     const int off = block_excl_scan(count, sm.scr(), total);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, acc = 0.0f;
@@ -516,38 +513,22 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
       __syncthreads();
       const int s1 = sm.scr()[8];
       const int tw = s1 - s0;
+      // window hit h -> (ray lane, slot): the ray's lane only publishes the map
       if (in_win) {
-        const HitRec* hr = a.hits + r * a.K;
-        for (int q = 0; q < count; ++q) {
-          const HitRec hh = hr[q];
-          const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hh.leaf));
-          const float tm = 0.5f * (hh.tin + hh.tout);
-          const float lx = -1.0f + static_cast<float>(hh.ijk & 1023u) * h;
-          const float ly = -1.0f + static_cast<float>((hh.ijk >> 10) & 1023u) * h;
-          const float lz = -1.0f + static_cast<float>(hh.ijk >> 20) * h;
-          RecL rc;
-          rc.leaf = hh.leaf;
-          rc.ux = fminf(fmaxf((ox + tm * dx - lx) * inv_h, 0.0f), 1.0f);
-          rc.uy = fminf(fmaxf((oy + tm * dy - ly) * inv_h, 0.0f), 1.0f);
-          rc.uz = fminf(fmaxf((oz + tm * dz - lz) * inv_h, 0.0f), 1.0f);
-          rc.tmid = tm;
-          rc.dt = hh.tout - hh.tin;
-          rc.T = 0.0f;
-          rc.pad = 0.0f;
-          rc.v0 = lc[0];
-          rc.v1 = lc[1];
-          sm.rec()[off - s0 + q] = rc;
-        }
+        for (int q = 0; q < count; ++q) sm.hmap()[off - s0 + q] = tid | (q << 16);
       }
       __syncthreads();
 
-      // gather + trilinear interpolation -> X[h][0..CI)
+      // per hit, in parallel: hit record, ray, corner ids, trilinear weights
+      // and the gather of the 8 corner rows -> X[h][0..CI); the first thread
+      // of each hit also writes the LDS hit record
       {
         constexpr int ROWB = CF::C * CF::EB;
         constexpr int TPH = ROWB / 16;
         constexpr int VPT = 16 / CF::EB;           // values per thread
         constexpr int HPP = kThreads / TPH;
         const int q = tid % TPH;
+        const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
         for (int hb = 0; hb < CF::WIN; hb += HPP) {
           const int hh = hb + tid / TPH;
           if (hh >= CF::WIN) break;
@@ -555,10 +536,36 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
 #pragma unroll
           for (int i = 0; i < VPT; ++i) v[i] = 0.0f;
           if (hh < tw) {
-            const RecL rc = sm.rec()[hh];
-            const int vid[8] = {rc.v0.x, rc.v0.y, rc.v0.z, rc.v0.w, rc.v1.x, rc.v1.y, rc.v1.z, rc.v1.w};
-            const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
-                        wz[2] = {1.0f - rc.uz, rc.uz};
+            const int mp = sm.hmap()[hh];
+            const int64_t rr = ray0 + (mp & 0xFFFF);
+            const HitRec hr = a.hits[rr * a.K + (mp >> 16)];
+            const float rox = a.o[3 * rr], roy = a.o[3 * rr + 1], roz = a.o[3 * rr + 2];
+            const float rdx = a.d[3 * rr], rdy = a.d[3 * rr + 1], rdz = a.d[3 * rr + 2];
+            const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hr.leaf));
+            const int4 c0 = lc[0], c1 = lc[1];
+            const float tm = 0.5f * (hr.tin + hr.tout);
+            const float lx = -1.0f + static_cast<float>(hr.ijk & 1023u) * h;
+            const float ly = -1.0f + static_cast<float>((hr.ijk >> 10) & 1023u) * h;
+            const float lz = -1.0f + static_cast<float>(hr.ijk >> 20) * h;
+            const float ux = fminf(fmaxf((rox + tm * rdx - lx) * inv_h, 0.0f), 1.0f);
+            const float uy = fminf(fmaxf((roy + tm * rdy - ly) * inv_h, 0.0f), 1.0f);
+            const float uz = fminf(fmaxf((roz + tm * rdz - lz) * inv_h, 0.0f), 1.0f);
+            if (q == 0) {
+              RecL rc;
+              rc.leaf = hr.leaf;
+              rc.ux = ux;
+              rc.uy = uy;
+              rc.uz = uz;
+              rc.tmid = tm;
+              rc.dt = hr.tout - hr.tin;
+              rc.T = 0.0f;
+              rc.pad = 0.0f;
+              rc.v0 = c0;
+              rc.v1 = c1;
+              sm.rec()[hh] = rc;
+            }
+            const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];

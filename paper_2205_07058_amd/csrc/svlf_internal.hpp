@@ -51,7 +51,8 @@ hipError_t launch_trace_public(const svlf_octree& oct, const float* o, const flo
                                int64_t n, int K, int32_t* leaf, float* tin, float* tout,
                                int32_t* cnt, hipStream_t s);
 hipError_t launch_trace_internal(const SceneTable& tab, const float* o, const float* d,
-                                 int K, HitRec* hits, int32_t* cnt, hipStream_t s);
+                                 int K, HitRec* hits, int32_t* cnt, unsigned long long* counter,
+                                 hipStream_t s);
 
 struct ShadeArgs {
   SceneTable tab;

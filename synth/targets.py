@@ -28,10 +28,9 @@ def _hit_ellipsoid(e, o, d):
     t1 = (-b + sq) / (2 * a)
     t = np.where(t0 > 0, t0, t1)
     ok &= t > 0
-    t = np.where(ok, t, np.inf)
-    p = o + t[:, None] * d
+    p = o + np.where(ok, t, 0.0)[:, None] * d
     n = np.where(ok[:, None], (p - e.c) @ e.A, 0.0)
-    return t, n
+    return np.where(ok, t, np.inf), n
 
 
 def _hit_box(bx, o, d):
