@@ -10,7 +10,8 @@ A timed step is one training pass over the batch: traversal, gather +
 trilinear interpolation, decoder, Eq. 3 compositing, MSE + L1 loss and the
 hand-written backward (svlf_train_step) with the BF16 decoder.  Also
 reported: the same step with the FP32 decoder, the forward render of one
-1600^2 view (BF16 and FP32), the dense Adam update timed separately, per-kernel
+1600^2 view (BF16 and FP32), whole optimisation steps with dense and with
+lazy (touched-row) Adam on the features, per-kernel
 durations (HIP events on the launch stream) with the roofline of the
 dominant kernel, PSNR of the BF16 render against the FP64 oracle on a seeded
 ray sample, and the oracle itself timed on the host.
@@ -158,19 +159,40 @@ def main():
                 f"{n_v * args.steps / ms * 1e3 / 1e6:.1f} M rays/s")
 
     if "adam" in sections:
+        # whole optimisation steps: the BF16 train pass, then Adam on the
+        # features (dense, or lazy over the touched rows) refreshing their
+        # BF16 copy, and dense Adam on the decoder parameters
         m = torch.zeros_like(scene.features)
         v = torch.zeros_like(scene.features)
+        mp, vp = torch.zeros_like(params), torch.zeros_like(params)
         st = [0]
+        tr = train_fn("bf16")
+        F_keep = scene.features.clone()
+        p_keep = params.clone()
 
-        def adam():
-            st[0] += 1
-            svlf.adam_step(scene.features, gF, m, v, 1e-3, 0.9, 0.999, 1e-8, st[0],
-                           bf16_out=scene.features_bf16, zero_grad=True)
-        ms, _ = timer.run(adam, args.steps, args.warmup)
-        res["adam_ms"] = ms / args.steps
-        log(f"dense Adam over {scene.features.numel()} features: {ms / args.steps:.3f} ms")
-        scene.features.copy_(T(F))
-        scene.refresh_bf16()
+        def step_with(lazy):
+            def fn():
+                st[0] += 1
+                tr()
+                upd = svlf.lazy_adam_step if lazy else svlf.adam_step
+                upd(scene.features, gF, m, v, 1e-3, 0.9, 0.999, 1e-8, st[0],
+                    bf16_out=scene.features_bf16, zero_grad=True)
+                svlf.adam_step(params, gp, mp, vp, 1e-3, 0.9, 0.999, 1e-8, st[0], zero_grad=True)
+            return fn
+        for lazy in (False, True):
+            ms, _ = timer.run(step_with(lazy), args.steps, args.warmup)
+            key = "lazy" if lazy else "dense"
+            res[f"step_{key}_adam_ms"] = ms / args.steps
+            log(f"train step + {key} Adam: {ms / args.steps:.3f} ms/step")
+            scene.features.copy_(F_keep)
+            params.copy_(p_keep)
+            scene.refresh_bf16()
+            m.zero_(), v.zero_(), mp.zero_(), vp.zero_(), gF.zero_(), gp.zero_()
+            st[0] = 0
+        tr()
+        res["touched_rows"] = float((gF != 0).any(dim=1).float().mean().item())
+        gF.zero_(), gp.zero_()
+        log(f"feature rows touched by one batch: {100 * res['touched_rows']:.1f}%")
 
     if "copy" in sections:
         # a plain device copy of known size: calibrates the HBM byte counters
@@ -264,13 +286,15 @@ def main():
                    "batch": n_b, "view_rays": n_v, "leaves": int(sc.leaf_ijk.shape[0]),
                    "vertices": int(sc.n_vertices), "hits_per_ray_batch": round(hits_b / n_b, 4),
                    "hits_per_ray_view": round(hits_v / n_v, 4)},
-        "step": "traversal + gather + decoder + Eq. 3 + loss + backward (svlf_train_step); Adam separate",
+        "step": "traversal + gather + decoder + Eq. 3 + loss + backward (svlf_train_step); optimiser steps reported separately",
         "train_fp32_rays_per_s": round(n_b / (res["train_fp32_ms"] * 1e-3), 1) if "train_fp32_ms" in res else None,
         "fwd_view_bf16_rays_per_s": round(n_v / (res["fwd_bf16_ms"] * 1e-3), 1) if "fwd_bf16_ms" in res else None,
         "fwd_view_fp32_rays_per_s": round(n_v / (res["fwd_fp32_ms"] * 1e-3), 1) if "fwd_fp32_ms" in res else None,
-        "adam_dense_ms": round(res["adam_ms"], 4) if "adam_ms" in res else None,
-        "train_bf16_with_adam_rays_per_s": round(n_b / ((res["train_bf16_ms"] + res["adam_ms"]) * 1e-3), 1)
-        if "adam_ms" in res and ms else None,
+        "train_bf16_with_dense_adam_rays_per_s": round(n_b / (res["step_dense_adam_ms"] * 1e-3), 1)
+        if "step_dense_adam_ms" in res else None,
+        "train_bf16_with_lazy_adam_rays_per_s": round(n_b / (res["step_lazy_adam_ms"] * 1e-3), 1)
+        if "step_lazy_adam_ms" in res else None,
+        "feature_rows_touched_per_batch": round(res["touched_rows"], 4) if "touched_rows" in res else None,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
         "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
         "device_copy_gbs": round(res["copy_gbs"], 1) if "copy_gbs" in res else None,

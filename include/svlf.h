@@ -17,6 +17,7 @@
  *   svlf_train_step     render + MSE/L1 loss + backward in one pass
  *   svlf_adam_step      Adam update of an FP32 parameter vector (section 4.5
  *                       trains with Adam)
+ *   svlf_lazy_adam_step Adam restricted to the feature rows a batch touched
  *
  * Conventions shared by every call
  * --------------------------------
@@ -164,6 +165,14 @@ typedef struct {
  * its two kernels, e.g. to reuse one traversal for several evaluations. */
 #define SVLF_FLAG_TRACE_ONLY 1
 #define SVLF_FLAG_REUSE_HITS 2
+/* SVLF_FLAG_VIEWDIR: the decoder input is the interpolated feature followed
+ * by the ray direction d as given (3 values), [psi(p; Z) | d], so that
+ * colour and density may depend on the viewing direction: the input the
+ * paper proposes for view-dependent appearance (section 6, limitations).
+ * mlp->widths[0] is then C + 3 (C = features per vertex); supported
+ * decoders 11-32-32-4 and 35-64-64-64-4.  The direction takes no gradient;
+ * grad_features keep C columns. */
+#define SVLF_FLAG_VIEWDIR 4
 
 /* ---------------------------------------------------------------- octree */
 
@@ -262,6 +271,22 @@ int svlf_adam_step(float* param, float* grad, float* m, float* v, int64_t n,
                    float lr, float beta1, float beta2, float eps, int64_t step_t,
                    uint16_t* bf16_out, int32_t zero_grad, void* stream);
 
+/* Lazy (row-sparse) Adam over a table of n_rows rows of row_len FP32
+ * entries (e.g. the per-vertex feature rows): a row takes the Adam update of
+ * svlf_adam_step, with bias corrections from the global step_t, only if its
+ * gradient row holds a nonzero entry; the parameters and both moments of any
+ * other row are left as they are.  This is the update of rows touched by the
+ * batch only (the dense optimiser's cost over an untouched row is what it
+ * saves; a row that no ray reached does not decay its moments).  The same
+ * bf16_out / zero_grad semantics as svlf_adam_step, applied to updated rows
+ * (untouched rows keep an all-zero gradient).  row_len: a multiple of 4 in
+ * [4, 256]; all arrays device, 16-byte aligned ([n_rows][row_len], bf16_out
+ * 8-byte aligned).  Errors: E_INVAL (NULL, misaligned, n_rows < 0),
+ * E_RANGE (hyper-parameters, step_t < 1), E_UNSUPPORTED (row_len). */
+int svlf_lazy_adam_step(float* param, float* grad, float* m, float* v, int64_t n_rows,
+                        int32_t row_len, float lr, float beta1, float beta2, float eps,
+                        int64_t step_t, uint16_t* bf16_out, int32_t zero_grad, void* stream);
+
 /* dst[i] = RNE bfloat16 bits of src[i] (device, n elements). */
 int svlf_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream);
 
@@ -270,7 +295,8 @@ int svlf_fill(float* dst, float value, int64_t n, void* stream);
 
 /* ---------------------------------------------------------------- diagnostics */
 
-/* Evaluates the decoder alone on X (device FP32 [n][C]) with the precision
+/* Evaluates the decoder alone on X (device FP32 [n][widths[0]]: C features,
+ * plus the 3 direction values with SVLF_FLAG_VIEWDIR) with the precision
  * of opts, writing the 4 raw outputs (before sigmoid/ReLU) to out (device
  * FP32 [n][4]).  Exposes the MLP of the render kernels for testing. */
 int svlf_mlp_forward(const svlf_mlp* mlp, const svlf_render_opts* opts, const float* X,

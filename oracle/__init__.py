@@ -16,10 +16,11 @@ What it computes (SVLF, arxiv 2205.07058, section 4):
   (section 4.5 activations), optical thickness (section 4 footnote) and
   alpha compositing (Eq. 3), in FP64, with an optional BF16-rounding mode;
   the hand-derived backward of all of it; the loss and its gradient.
+* ``optim``   -- Adam (section 4.5), dense and restricted to touched rows.
 
 Every function states the passage it follows.  Parity status: every function
 is pinned by the ``-m "not gpu"`` tests (brute force, exact rationals, closed
 forms, invariants and finite differences); none is "parity unpinned".
 """
 
-from . import octree, trace, render  # noqa: F401
+from . import octree, trace, render, optim  # noqa: F401

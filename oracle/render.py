@@ -17,6 +17,11 @@ Follows SVLF section 4 with the single-decoder reading used by the library:
   accumulated opacity use the same weights (depth = sum w_i t_mid_i,
   acc = sum w_i); a ray with no hits gives zeros.
 
+``viewdir=True`` appends the ray direction d (3 values) to the decoder input,
+x_in = [psi(p; Z) | d]: the view-direction input the paper proposes for its
+colour decoder to capture view-dependent appearance (section 6,
+limitations); with one decoder it is an input of the whole MLP.
+
 ``bf16=True`` rounds (round to nearest even) the features, the weights, the
 MLP input x and every hidden activation after ReLU to bfloat16 before use;
 in the backward it also rounds each layer's incoming gradient (dL/dz) to
@@ -98,7 +103,7 @@ class RenderState:
 
 
 def render(octree: Octree, features, params, widths, o, d, hits, tau_mode="voxel",
-           bf16=False):
+           bf16=False, viewdir=False):
     """Forward render.  ``hits`` = (hit_leaf, hit_tin, hit_tout, hit_count)
     from ``trace.trace_hits``.  Returns (rgb (n,3), depth (n,), acc (n,),
     state)."""
@@ -125,7 +130,10 @@ def render(octree: Octree, features, params, widths, o, d, hits, tau_mode="voxel
     wj = interpolation_weights(u)
     corners = octree.leaf_corners[leaf]                 # (m, 8)
     X = np.einsum("mj,mjc->mc", wj, F[corners])
-    out, acts, pres = mlp_forward(params, widths, X, bf16)
+    X_in = np.concatenate([X, d[ray_i]], axis=1) if viewdir else X
+    if widths[0] != X_in.shape[1]:
+        raise ValueError("decoder input width does not match the features (+3 with viewdir)")
+    out, acts, pres = mlp_forward(params, widths, X_in, bf16)
     c = sigmoid(out[:, :3])
     sigma = np.maximum(out[:, 3], 0.0)
     dt = t1 - t0
@@ -194,7 +202,7 @@ def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
         if li > 0:
             g_z = np.where(st.pres[li - 1] > 0.0, g_a, 0.0)
         else:
-            g_X = g_a
+            g_X = g_a[:, :st.C]          # the view direction takes no gradient
     grads.reverse()
     grad_params = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     grad_F = np.zeros((st.n_vertices, st.C))

@@ -15,9 +15,9 @@ from . import svlf
 
 class _SVLFRender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, features, params, ray_o, ray_d, scene, widths, K, tau_mode, precision):
+    def forward(ctx, features, params, ray_o, ray_d, scene, widths, K, tau_mode, precision, flags):
         sc = svlf.DeviceScene(scene.octree, features.detach(), scene.features_bf16)
-        opts = svlf.make_opts(K, tau_mode, precision)
+        opts = svlf.make_opts(K, tau_mode, precision, flags)
         n = ray_o.shape[0]
         rgb, depth, acc = svlf.render([sc], [n], params.detach(), widths, opts, ray_o, ray_d)
         ctx.save_for_backward(features, params, ray_o, ray_d)
@@ -37,13 +37,16 @@ class _SVLFRender(torch.autograd.Function):
         sc = svlf.DeviceScene(ctx.scene.octree, features.detach(), ctx.scene.features_bf16)
         svlf.render_backward([sc], [n], params.detach(), ctx.widths, ctx.opts, ray_o, ray_d,
                              g_rgb, g_depth, g_acc, [gF], gp)
-        return gF, gp, None, None, None, None, None, None, None
+        return gF, gp, None, None, None, None, None, None, None, None
 
 
 def render(scene: "svlf.DeviceScene", params, widths, ray_o, ray_d, K, tau_mode="voxel",
-           precision="fp32", features=None):
+           precision="fp32", features=None, viewdir=False):
     """Differentiable render: returns (rgb, depth, acc).  Gradients flow to
     ``features`` (default: scene.features) and ``params``.  In BF16 precision
-    the scene's BF16 feature copy must match ``features``."""
+    the scene's BF16 feature copy must match ``features``.  ``viewdir``
+    appends the ray direction to the decoder input (widths[0] = C + 3)."""
     feats = scene.features if features is None else features
-    return _SVLFRender.apply(feats, params, ray_o, ray_d, scene, tuple(widths), K, tau_mode, precision)
+    flags = svlf.FLAG_VIEWDIR if viewdir else 0
+    return _SVLFRender.apply(feats, params, ray_o, ray_d, scene, tuple(widths), K, tau_mode, precision,
+                             flags)

@@ -52,7 +52,9 @@ struct MlpShape {
   int64_t n_params;
 };
 
-int check_mlp(const svlf_mlp* mlp, MlpShape* sh, const char* who) {
+// The decoder input is the C interpolated features, followed by the ray
+// direction (3 values) when `viewdir` is set.
+int check_mlp(const svlf_mlp* mlp, bool viewdir, MlpShape* sh, const char* who) {
   if (mlp == nullptr || mlp->params == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "mlp or mlp->params is NULL"));
   const int L = mlp->n_layers;
@@ -64,17 +66,22 @@ int check_mlp(const svlf_mlp* mlp, MlpShape* sh, const char* who) {
       return fail(SVLF_E_INVAL, who_str(who, "non-positive layer width"));
     np += static_cast<int64_t>(mlp->widths[l]) * mlp->widths[l + 1] + mlp->widths[l + 1];
   }
-  const int c = mlp->widths[0], h = mlp->widths[1];
+  const int c = mlp->widths[0] - (viewdir ? 3 : 0), h = mlp->widths[1];
   if (mlp->widths[L] != 4)
     return fail(SVLF_E_INVAL, who_str(who, "the last layer must have 4 outputs (RGB, sigma)"));
   if (c != 8 && c != 16 && c != 32)
-    return fail(SVLF_E_UNSUPPORTED, who_str(who, "C must be 8, 16 or 32"));
+    return fail(SVLF_E_UNSUPPORTED,
+                who_str(who, viewdir ? "widths[0] must be C + 3 with C = 8, 16 or 32"
+                                     : "C must be 8, 16 or 32"));
   if (h != 32 && h != 64)
     return fail(SVLF_E_UNSUPPORTED, who_str(who, "hidden width must be 32 or 64"));
   for (int l = 1; l < L; ++l)
     if (mlp->widths[l] != h)
       return fail(SVLF_E_UNSUPPORTED, who_str(who, "hidden layers must have equal widths"));
   if (L - 1 > 4) return fail(SVLF_E_UNSUPPORTED, who_str(who, "at most 4 hidden layers"));
+  if (viewdir && !((c == 8 && h == 32 && L == 3) || (c == 32 && h == 64 && L == 4)))
+    return fail(SVLF_E_UNSUPPORTED,
+                who_str(who, "view-direction input: decoders 11-32-32-4 and 35-64-64-64-4 only"));
   sh->C = c;
   sh->H = h;
   sh->n_hidden = L - 1;
@@ -90,7 +97,7 @@ int check_opts(const svlf_render_opts* opts, const char* who) {
     return fail(SVLF_E_RANGE, who_str(who, "unknown tau_mode"));
   if (opts->precision != SVLF_FP32 && opts->precision != SVLF_BF16)
     return fail(SVLF_E_RANGE, who_str(who, "unknown precision"));
-  if (opts->flags & ~(SVLF_FLAG_TRACE_ONLY | SVLF_FLAG_REUSE_HITS))
+  if (opts->flags & ~(SVLF_FLAG_TRACE_ONLY | SVLF_FLAG_REUSE_HITS | SVLF_FLAG_VIEWDIR))
     return fail(SVLF_E_INVAL, who_str(who, "unknown flags"));
   if ((opts->flags & SVLF_FLAG_TRACE_ONLY) && (opts->flags & SVLF_FLAG_REUSE_HITS))
     return fail(SVLF_E_INVAL, who_str(who, "TRACE_ONLY and REUSE_HITS exclude each other"));
@@ -145,9 +152,8 @@ int make_table(const svlf_scene* scenes, int n_scenes, const int64_t* offs, bool
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace: [hit slots n*K][counts n][per-block dW partials][per-block loss]
-// [ray-refill counter of the traversal]
 struct WsLayout {
-  size_t hits, cnt, partials, loss, counter, total;
+  size_t hits, cnt, partials, loss, total;
 };
 
 WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
@@ -161,8 +167,6 @@ WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
   off = align256(off + static_cast<size_t>(shade_grid_limit()) * n_params * sizeof(float));
   w.loss = off;
   off = align256(off + static_cast<size_t>(shade_grid_limit()) * sizeof(float));
-  w.counter = off;
-  off = align256(off + sizeof(unsigned long long));
   w.total = off;
   return w;
 }
@@ -175,7 +179,7 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   int rc = check_opts(opts, who);
   if (rc) return rc;
   MlpShape sh;
-  rc = check_mlp(mlp, &sh, who);
+  rc = check_mlp(mlp, (opts->flags & SVLF_FLAG_VIEWDIR) != 0, &sh, who);
   if (rc) return rc;
   const bool need_grads = mode != kForward;
   rc = make_table(scenes, n_scenes, offs, opts->precision == SVLF_BF16, grad_features, need_grads,
@@ -201,14 +205,14 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   a.C = sh.C;
   a.H = sh.H;
   a.n_hidden = sh.n_hidden;
+  a.viewdir = (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0;
   a.params = mlp->params;
   a.n_params = sh.n_params;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (!(opts->flags & SVLF_FLAG_REUSE_HITS)) {
     e = launch_trace_internal(a.tab, ray_o, ray_d, opts->K, const_cast<HitRec*>(a.hits),
-                              const_cast<int32_t*>(a.cnt),
-                              reinterpret_cast<unsigned long long*>(base + w.counter), s);
+                              const_cast<int32_t*>(a.cnt), s);
     if (e != hipSuccess) return hip_fail(e, who);
   }
   if (opts->flags & SVLF_FLAG_TRACE_ONLY) return SVLF_OK;
@@ -306,7 +310,7 @@ size_t svlf_workspace_bytes(const svlf_mlp* mlp, const svlf_render_opts* opts, i
   const char* who = "svlf_workspace_bytes";
   if (check_opts(opts, who)) return 0;
   MlpShape sh;
-  if (check_mlp(mlp, &sh, who)) return 0;
+  if (check_mlp(mlp, (opts->flags & SVLF_FLAG_VIEWDIR) != 0, &sh, who)) return 0;
   if (n_rays < 0) {
     fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
     return 0;
@@ -392,6 +396,35 @@ int svlf_adam_step(float* param, float* grad, float* m, float* v, int64_t n, flo
   return SVLF_OK;
 }
 
+int svlf_lazy_adam_step(float* param, float* grad, float* m, float* v, int64_t n_rows,
+                        int32_t row_len, float lr, float beta1, float beta2, float eps,
+                        int64_t step_t, uint16_t* bf16_out, int32_t zero_grad, void* stream) {
+  const char* who = "svlf_lazy_adam_step";
+  if (n_rows < 0) return fail(SVLF_E_INVAL, who_str(who, "n_rows < 0"));
+  if (row_len < 4 || row_len > 256 || row_len % 4 != 0)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "row_len must be a multiple of 4 in [4, 256]"));
+  if (step_t < 1) return fail(SVLF_E_RANGE, who_str(who, "step_t must be >= 1"));
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+      !std::isfinite(lr))
+    return fail(SVLF_E_RANGE, who_str(who, "invalid hyper-parameters"));
+  if (n_rows == 0) return SVLF_OK;
+  if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "NULL array"));
+  auto misaligned = [](const void* q, uintptr_t a) {
+    return (reinterpret_cast<uintptr_t>(q) & (a - 1)) != 0;
+  };
+  if (misaligned(param, 16) || misaligned(grad, 16) || misaligned(m, 16) || misaligned(v, 16) ||
+      (bf16_out != nullptr && misaligned(bf16_out, 8)))
+    return fail(SVLF_E_INVAL, who_str(who, "arrays must be 16-byte aligned (bf16_out 8-byte)"));
+  const double bc1 = 1.0 - std::pow(static_cast<double>(beta1), static_cast<double>(step_t));
+  const double bc2 = 1.0 - std::pow(static_cast<double>(beta2), static_cast<double>(step_t));
+  hipError_t e = launch_lazy_adam(param, grad, m, v, n_rows, row_len, lr, beta1, beta2, eps,
+                                  static_cast<float>(bc1), static_cast<float>(bc2), bf16_out,
+                                  zero_grad, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, who);
+  return SVLF_OK;
+}
+
 int svlf_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream) {
   if (n < 0) return fail(SVLF_E_INVAL, "svlf_to_bf16: n < 0");
   if (n == 0) return SVLF_OK;
@@ -416,13 +449,14 @@ int svlf_mlp_forward(const svlf_mlp* mlp, const svlf_render_opts* opts, const fl
   int rc = check_opts(opts, who);
   if (rc) return rc;
   MlpShape sh;
-  rc = check_mlp(mlp, &sh, who);
+  rc = check_mlp(mlp, (opts->flags & SVLF_FLAG_VIEWDIR) != 0, &sh, who);
   if (rc) return rc;
   if (n < 0) return fail(SVLF_E_INVAL, who_str(who, "n < 0"));
   if (n == 0) return SVLF_OK;
   if (X == nullptr || out == nullptr) return fail(SVLF_E_INVAL, who_str(who, "NULL array"));
-  hipError_t e = launch_mlp_forward(mlp->params, sh.C, sh.H, sh.n_hidden, opts->precision, X, n,
-                                    out, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_mlp_forward(mlp->params, sh.C, sh.H, sh.n_hidden,
+                                    (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0, opts->precision, X,
+                                    n, out, static_cast<hipStream_t>(stream));
   if (e == hipErrorNotSupported)
     return fail(SVLF_E_UNSUPPORTED, who_str(who, "no kernel for this MLP shape / precision"));
   if (e != hipSuccess) return hip_fail(e, who);

@@ -109,21 +109,24 @@ constexpr int par_b(int l, int C, int H, int NH) {
 }
 // dW tiles per layer: (out tiles) x (in tiles)
 constexpr int dw_mt(int l, int H, int NH) { return out_w(l, H, NH) / 32; }
-constexpr int dw_nt(int l, int H) { return l == 0 ? 1 : H / 32; }
-constexpr int dw_tile_off(int l, int H, int NH) {
+constexpr int dw_nt(int l, int H, int CIN) { return l == 0 ? (CIN + 31) / 32 : H / 32; }
+constexpr int dw_tile_off(int l, int H, int NH, int CIN) {
   int o = 0;
-  for (int i = 0; i < l; ++i) o += dw_mt(i, H, NH) * dw_nt(i, H);
+  for (int i = 0; i < l; ++i) o += dw_mt(i, H, NH) * dw_nt(i, H, CIN);
   return o;
 }
 constexpr int align16(int x) { return (x + 15) & ~15; }
+constexpr int align8(int x) { return (x + 7) & ~7; }
 
-template <int P, int C_, int H_, int NH_, int MODE_>
+// VD = 1: the decoder input is [psi (C) | ray direction (3)].
+template <int P, int C_, int H_, int NH_, int MODE_, int VD_ = 0>
 struct Cfg {
   static constexpr bool BF = P == 1;
-  static constexpr int C = C_, H = H_, NH = NH_, MODE = MODE_;
+  static constexpr int C = C_, H = H_, NH = NH_, MODE = MODE_, VD = VD_;
   static constexpr bool BWD = MODE != kForward;
   static constexpr int KS = BF ? 16 : 2;            // K per MFMA
-  static constexpr int CI = (BF && C < 16) ? 16 : C;  // padded decoder input
+  static constexpr int CIN = C + 3 * VD;            // decoder input width
+  static constexpr int CI = BF ? align16(CIN) : align8(CIN);  // padded to the K steps
   static constexpr int NL = NH + 1;
   static constexpr int MTH = H / 32;
   static constexpr int WIN = (BWD && !BF) ? 64 : 128;
@@ -134,8 +137,8 @@ struct Cfg {
   static constexpr int FWD_ELEMS = fwd_off(NL, CI, H, NH);
   static constexpr int BWD_ELEMS = BWD ? bwd_off(NL, H, NH) : 0;
   static constexpr int BIAS_ELEMS = bias_off(NL, H, NH);
-  static constexpr int NPARAMS = par_w(NL, C, H, NH);
-  static constexpr int NDW = dw_tile_off(NL, H, NH);          // dW tiles
+  static constexpr int NPARAMS = par_w(NL, CIN, H, NH);
+  static constexpr int NDW = dw_tile_off(NL, H, NH, CIN);     // dW tiles
   static constexpr int DW_SLOTS = (NDW + kWaves - 1) / kWaves;
   static constexpr int NBIAS = NH * H + 4;
   static constexpr int XS = CI + (BF ? 8 : 4);                  // X row stride
@@ -148,12 +151,13 @@ struct Cfg {
   static constexpr int L_REC = align16(L_BI + BIAS_ELEMS * 4);
   static constexpr int L_X = align16(L_REC + WIN * 64);
   static constexpr int L_OUT = align16(L_X + WIN * XS * EB);
-  static constexpr int L_GZ = align16(L_OUT + WIN * 16);
+  static constexpr int L_GZ = align16(L_OUT + WIN * 32);
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
   static constexpr int L_MAP = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
   static constexpr int L_SCR = align16(L_MAP + WIN * 4);
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
+  static_assert(C <= 32 && CI <= TROWS, "feature gradients come from one 32-row tile");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
   static_assert(!BWD || WIN * C * 4 <= 2 * TROWS * TS * EB, "dL/dx staging fits in GZ + AT");
 };
@@ -219,10 +223,10 @@ __device__ __forceinline__ void build_packs(const Smem<CF>& sm, const float* __r
   static_for<CF::NL>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     constexpr int IW = in_w(l, CF::CI, CF::H), OW = out_w(l, CF::H, CF::NH);
-    constexpr int IR = in_real(l, CF::C, CF::H), OR = out_real(l, CF::H, CF::NH);
+    constexpr int IR = in_real(l, CF::CIN, CF::H), OR = out_real(l, CF::H, CF::NH);
     constexpr int STEPS = IW / CF::KS;
-    const float* W = params + par_w(l, CF::C, CF::H, CF::NH);
-    const float* b = params + par_b(l, CF::C, CF::H, CF::NH);
+    const float* W = params + par_w(l, CF::CIN, CF::H, CF::NH);
+    const float* b = params + par_b(l, CF::CIN, CF::H, CF::NH);
     typename CF::Elem* fp = sm.fpack() + fwd_off(l, CF::CI, CF::H, CF::NH);
     for (int e = threadIdx.x; e < OW * IW; e += kThreads) {
       const int j = e % E, lane = (e / E) % 64, s = (e / (E * 64)) % STEPS, mt = e / (E * 64 * STEPS);
@@ -460,7 +464,7 @@ __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf
 // ------------------------------------------------------------ the kernel
 
 template <class CF>
-__global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
+__global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a) {
   const Smem<CF> sm{};
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5;
 
@@ -521,50 +525,73 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
 
       // per hit, in parallel: hit record, ray, corner ids, trilinear weights
       // and the gather of the 8 corner rows -> X[h][0..CI); the first thread
-      // of each hit also writes the LDS hit record
+      // of each hit also writes the LDS hit record.  A thread serves NPASS
+      // hits; the loads of a group of passes are all issued before any is
+      // consumed.
       {
         constexpr int ROWB = CF::C * CF::EB;
         constexpr int TPH = ROWB / 16;
         constexpr int VPT = 16 / CF::EB;           // values per thread
         constexpr int HPP = kThreads / TPH;
+        constexpr int NPASS = (CF::WIN + HPP - 1) / HPP;
+        constexpr int GRP = (CF::BWD && NPASS >= 2) ? 2 : 1;
         const int q = tid % TPH;
         const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
-        for (int hb = 0; hb < CF::WIN; hb += HPP) {
-          const int hh = hb + tid / TPH;
-          if (hh >= CF::WIN) break;
-          float v[VPT];
+#pragma unroll 1
+        for (int pb = 0; pb < NPASS; pb += GRP) {
+          int hh[GRP];
+          bool val[GRP];
+          HitRec hr[GRP];
+          float ro[GRP][3], rd[GRP][3];
+          int4 c0[GRP], c1[GRP];
 #pragma unroll
-          for (int i = 0; i < VPT; ++i) v[i] = 0.0f;
-          if (hh < tw) {
-            const int mp = sm.hmap()[hh];
-            const int64_t rr = ray0 + (mp & 0xFFFF);
-            const HitRec hr = a.hits[rr * a.K + (mp >> 16)];
-            const float rox = a.o[3 * rr], roy = a.o[3 * rr + 1], roz = a.o[3 * rr + 2];
-            const float rdx = a.d[3 * rr], rdy = a.d[3 * rr + 1], rdz = a.d[3 * rr + 2];
-            const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hr.leaf));
-            const int4 c0 = lc[0], c1 = lc[1];
-            const float tm = 0.5f * (hr.tin + hr.tout);
-            const float lx = -1.0f + static_cast<float>(hr.ijk & 1023u) * h;
-            const float ly = -1.0f + static_cast<float>((hr.ijk >> 10) & 1023u) * h;
-            const float lz = -1.0f + static_cast<float>(hr.ijk >> 20) * h;
-            const float ux = fminf(fmaxf((rox + tm * rdx - lx) * inv_h, 0.0f), 1.0f);
-            const float uy = fminf(fmaxf((roy + tm * rdy - ly) * inv_h, 0.0f), 1.0f);
-            const float uz = fminf(fmaxf((roz + tm * rdz - lz) * inv_h, 0.0f), 1.0f);
+          for (int k = 0; k < GRP; ++k) {
+            hh[k] = (pb + k) * HPP + tid / TPH;
+            val[k] = hh[k] < tw;
+            if (val[k]) {
+              const int mp = sm.hmap()[hh[k]];
+              const int64_t rr = ray0 + (mp & 0xFFFF);
+              hr[k] = a.hits[rr * a.K + (mp >> 16)];
+              ro[k][0] = a.o[3 * rr]; ro[k][1] = a.o[3 * rr + 1]; ro[k][2] = a.o[3 * rr + 2];
+              rd[k][0] = a.d[3 * rr]; rd[k][1] = a.d[3 * rr + 1]; rd[k][2] = a.d[3 * rr + 2];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < GRP; ++k) {
+            if (val[k]) {
+              const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hr[k].leaf));
+              c0[k] = lc[0];
+              c1[k] = lc[1];
+            }
+          }
+          float v[GRP][VPT];
+#pragma unroll
+          for (int k = 0; k < GRP; ++k) {
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) v[k][i] = 0.0f;
+            if (!val[k]) continue;
+            const float tm = 0.5f * (hr[k].tin + hr[k].tout);
+            const float lx = -1.0f + static_cast<float>(hr[k].ijk & 1023u) * h;
+            const float ly = -1.0f + static_cast<float>((hr[k].ijk >> 10) & 1023u) * h;
+            const float lz = -1.0f + static_cast<float>(hr[k].ijk >> 20) * h;
+            const float ux = fminf(fmaxf((ro[k][0] + tm * rd[k][0] - lx) * inv_h, 0.0f), 1.0f);
+            const float uy = fminf(fmaxf((ro[k][1] + tm * rd[k][1] - ly) * inv_h, 0.0f), 1.0f);
+            const float uz = fminf(fmaxf((ro[k][2] + tm * rd[k][2] - lz) * inv_h, 0.0f), 1.0f);
             if (q == 0) {
               RecL rc;
-              rc.leaf = hr.leaf;
+              rc.leaf = hr[k].leaf;
               rc.ux = ux;
               rc.uy = uy;
               rc.uz = uz;
               rc.tmid = tm;
-              rc.dt = hr.tout - hr.tin;
+              rc.dt = hr[k].tout - hr[k].tin;
               rc.T = 0.0f;
               rc.pad = 0.0f;
-              rc.v0 = c0;
-              rc.v1 = c1;
-              sm.rec()[hh] = rc;
+              rc.v0 = c0[k];
+              rc.v1 = c1[k];
+              sm.rec()[hh[k]] = rc;
             }
-            const int vid[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+            const int vid[8] = {c0[k].x, c0[k].y, c0[k].z, c0[k].w, c1[k].x, c1[k].y, c1[k].z, c1[k].w};
             const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -574,24 +601,33 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
                 const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  v[2 * i] += wj * bf16_f32(static_cast<uint16_t>(w4[i] & 0xFFFFu));
-                  v[2 * i + 1] += wj * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
+                  v[k][2 * i] += wj * bf16_f32(static_cast<uint16_t>(w4[i] & 0xFFFFu));
+                  v[k][2 * i + 1] += wj * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
                 }
               } else {
                 const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * CF::C + 4 * q);
-                v[0] += wj * f.x;
-                v[1] += wj * f.y;
-                v[2] += wj * f.z;
-                v[3] += wj * f.w;
+                v[k][0] += wj * f.x;
+                v[k][1] += wj * f.y;
+                v[k][2] += wj * f.z;
+                v[k][3] += wj * f.w;
               }
             }
           }
-          typename CF::Elem* xr = sm.X() + hh * CF::XS + VPT * q;
 #pragma unroll
-          for (int i = 0; i < VPT; ++i) xr[i] = to_elem<CF>(v[i]);
-          if (CF::CI > CF::C && q == 0) {
+          for (int k = 0; k < GRP; ++k) {
+            if (hh[k] >= CF::WIN) continue;
+            typename CF::Elem* xr = sm.X() + hh[k] * CF::XS + VPT * q;
 #pragma unroll
-            for (int i = CF::C; i < CF::CI; ++i) sm.X()[hh * CF::XS + i] = to_elem<CF>(0.0f);
+            for (int i = 0; i < VPT; ++i) xr[i] = to_elem<CF>(v[k][i]);
+            if (CF::CI > CF::C && q == 0) {
+              // view direction (VD) and zero padding up to the K steps
+#pragma unroll
+              for (int i = CF::C; i < CF::CI; ++i) {
+                float xv = 0.0f;
+                if (CF::VD && i < CF::C + 3 && val[k]) xv = rd[k][i - CF::C];
+                sm.X()[hh[k] * CF::XS + i] = to_elem<CF>(xv);
+              }
+            }
           }
         }
       }
@@ -603,32 +639,38 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
       const bool has_tile = wave < CF::NTILE && n0 < tw;
       if (has_tile) {
         const f32x16 o = mlp_tile<CF, CF::BWD>(sm, n0, lane, act);
-        if (g == 0) {
-          const f32x4 ov = {o[0], o[1], o[2], o[3]};
-          *reinterpret_cast<f32x4*>(sm.out() + 4 * (n0 + lane)) = ov;
+        // per-hit epilogue, one hit per lane: colour, opacity and
+        // transmittance factor of the segment (section 4 footnote, Eq. 3)
+        if (g == 0 && n0 + lane < tw) {
+          const RecL& rc = sm.rec()[n0 + lane];
+          const float ft = a.tau_mode == SVLF_TAU_VOXEL ? rc.dt * inv_h
+                           : a.tau_mode == SVLF_TAU_WORLD ? rc.dt : 1.0f;
+          const float tau = fmaxf(o[3], 0.0f) * ft;
+          const f32x4 va = {sigmoidf_(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), -expm1f(-tau)};
+          const f32x4 vb = {expf(-tau), o[3] > 0.0f ? ft : 0.0f, rc.tmid, 0.0f};
+          *reinterpret_cast<f32x4*>(sm.out() + 8 * (n0 + lane)) = va;
+          *reinterpret_cast<f32x4*>(sm.out() + 8 * (n0 + lane) + 4) = vb;
         }
       }
       __syncthreads();
 
       // Eq. 3 front to back (owner lanes), and its backward
+      // Eq. 3 front to back (owner lanes), and its backward
       if (in_win) {
         const int p0 = off - s0;
         float T = 1.0f;
         for (int q = 0; q < count; ++q) {
-          const f32x4 o = *reinterpret_cast<const f32x4*>(sm.out() + 4 * (p0 + q));
-          RecL& rc = sm.rec()[p0 + q];
-          const float sig = fmaxf(o[3], 0.0f);
-          const float ft = a.tau_mode == SVLF_TAU_VOXEL ? rc.dt * inv_h
-                           : a.tau_mode == SVLF_TAU_WORLD ? rc.dt : 1.0f;
-          const float tau = sig * ft;
-          const float w = T * -expm1f(-tau);
-          cr += w * sigmoidf_(o[0]);
-          cg += w * sigmoidf_(o[1]);
-          cb += w * sigmoidf_(o[2]);
-          dep += w * rc.tmid;
+          float* hp = sm.out() + 8 * (p0 + q);
+          const f32x4 va = *reinterpret_cast<const f32x4*>(hp);
+          const f32x4 vb = *reinterpret_cast<const f32x4*>(hp + 4);
+          const float w = T * va[3];
+          cr += w * va[0];
+          cg += w * va[1];
+          cb += w * va[2];
+          dep += w * vb[2];
           acc += w;
-          if constexpr (CF::BWD) rc.T = T;
-          T *= expf(-tau);
+          if constexpr (CF::BWD) hp[7] = T;
+          T *= vb[0];
         }
         if constexpr (CF::BWD) {
           float gr, gg, gb, gd, ga;
@@ -650,30 +692,26 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           }
           float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f, St = 0.0f, Sa = 0.0f;
           for (int q = count - 1; q >= 0; --q) {
-            float* op = sm.out() + 4 * (p0 + q);
-            const f32x4 o = *reinterpret_cast<const f32x4*>(op);
-            const RecL rc = sm.rec()[p0 + q];
-            const float sig = fmaxf(o[3], 0.0f);
-            const float ft = a.tau_mode == SVLF_TAU_VOXEL ? rc.dt * inv_h
-                             : a.tau_mode == SVLF_TAU_WORLD ? rc.dt : 1.0f;
-            const float tau = sig * ft;
-            const float e = expf(-tau);
-            const float w = rc.T * -expm1f(-tau);
-            const float Tn = rc.T * e;
-            const float c0 = sigmoidf_(o[0]), c1 = sigmoidf_(o[1]), c2 = sigmoidf_(o[2]);
+            float* hp = sm.out() + 8 * (p0 + q);
+            const f32x4 va = *reinterpret_cast<const f32x4*>(hp);
+            const f32x4 vb = *reinterpret_cast<const f32x4*>(hp + 4);
+            const float Tq = vb[3];
+            const float w = Tq * va[3];
+            const float Tn = Tq * vb[0];
+            const float c0 = va[0], c1 = va[1], c2 = va[2], tm = vb[2];
             const float gtau = gr * (Tn * c0 - Sr) + gg * (Tn * c1 - Sg) + gb * (Tn * c2 - Sb) +
-                               gd * (Tn * rc.tmid - St) + ga * (Tn - Sa);
+                               gd * (Tn * tm - St) + ga * (Tn - Sa);
             Sr += w * c0;
             Sg += w * c1;
             Sb += w * c2;
-            St += w * rc.tmid;
+            St += w * tm;
             Sa += w;
             f32x4 go;
             go[0] = gr * w * c0 * (1.0f - c0);
             go[1] = gg * w * c1 * (1.0f - c1);
             go[2] = gb * w * c2 * (1.0f - c2);
-            go[3] = o[3] > 0.0f ? gtau * ft : 0.0f;
-            *reinterpret_cast<f32x4*>(op) = go;
+            go[3] = gtau * vb[1];
+            *reinterpret_cast<f32x4*>(hp) = go;
           }
         }
       }
@@ -685,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
 #pragma unroll
         for (int mt = 0; mt < CF::MTH; ++mt) gz[mt] = zero16();
         if (has_tile && g == 0 && n0 + lane < tw) {
-          const f32x4 go = *reinterpret_cast<const f32x4*>(sm.out() + 4 * (n0 + lane));
+          const f32x4 go = *reinterpret_cast<const f32x4*>(sm.out() + 8 * (n0 + lane));
           gz[0][0] = go[0];
           gz[0][1] = go[1];
           gz[0][2] = go[2];
@@ -717,8 +755,8 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
           __syncthreads();
           // owned dW tiles of layer l: K = the window's hits
           {
-            constexpr int MT = dw_mt(l, CF::H, CF::NH), NT = dw_nt(l, CF::H);
-            constexpr int T0 = dw_tile_off(l, CF::H, CF::NH);
+            constexpr int MT = dw_mt(l, CF::H, CF::NH), NT = dw_nt(l, CF::H, CF::CIN);
+            constexpr int T0 = dw_tile_off(l, CF::H, CF::NH, CF::CIN);
             constexpr int KSTEPS = CF::WIN / CF::KS;
             static_for<MT * NT>([&](auto tc) {
               constexpr int t = decltype(tc)::value;
@@ -836,9 +874,9 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
     float* part = a.ws_partials + static_cast<int64_t>(blockIdx.x) * CF::NPARAMS;
     static_for<CF::NL>([&](auto lc) {
       constexpr int l = decltype(lc)::value;
-      constexpr int MT = dw_mt(l, CF::H, CF::NH), NT = dw_nt(l, CF::H);
-      constexpr int T0 = dw_tile_off(l, CF::H, CF::NH);
-      constexpr int IR = in_real(l, CF::C, CF::H), OR = out_real(l, CF::H, CF::NH);
+      constexpr int MT = dw_mt(l, CF::H, CF::NH), NT = dw_nt(l, CF::H, CF::CIN);
+      constexpr int T0 = dw_tile_off(l, CF::H, CF::NH, CF::CIN);
+      constexpr int IR = in_real(l, CF::CIN, CF::H), OR = out_real(l, CF::H, CF::NH);
       static_for<MT * NT>([&](auto tc) {
         constexpr int t = decltype(tc)::value;
         constexpr int tau_i = T0 + t, mt = t / NT, nt = t % NT, slot = tau_i / kWaves;
@@ -847,7 +885,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int rowo = 32 * mt + drow(i, g);
-            if (rowo < OR && col < IR) part[par_w(l, CF::C, CF::H, CF::NH) + rowo * IR + col] = dw[slot][i];
+            if (rowo < OR && col < IR) part[par_w(l, CF::CIN, CF::H, CF::NH) + rowo * IR + col] = dw[slot][i];
           }
         }
       });
@@ -858,7 +896,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ShadeArgs a) {
         int pb = 0;
         static_for<CF::NL>([&](auto lc) {
           constexpr int l = decltype(lc)::value;
-          if (l == db_layer) pb = par_b(l, CF::C, CF::H, CF::NH);
+          if (l == db_layer) pb = par_b(l, CF::CIN, CF::H, CF::NH);
         });
         part[pb + db_row] = db;
       }
@@ -886,7 +924,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_rows(const float* __restrict__
     for (int e = tid; e < CF::WIN * CF::CI; e += kThreads) {
       const int hh = e / CF::CI, c = e % CF::CI;
       const int64_t row = base + hh;
-      sm.X()[hh * CF::XS + c] = to_elem<CF>((row < n && c < CF::C) ? X[row * CF::C + c] : 0.0f);
+      sm.X()[hh * CF::XS + c] = to_elem<CF>((row < n && c < CF::CIN) ? X[row * CF::CIN + c] : 0.0f);
     }
     __syncthreads();
     ActTile<CF::BF> act[CF::NH][CF::MTH];
@@ -937,16 +975,16 @@ hipError_t run(const ShadeArgs& a, hipStream_t s, int* grid_used) {
   return hipGetLastError();
 }
 
-template <int P, int C, int H, int NH>
+template <int P, int C, int H, int NH, int VD>
 hipError_t run_mode(const ShadeArgs& a, int mode, hipStream_t s, int* grid) {
-  if (mode == kForward) return run<Cfg<P, C, H, NH, kForward>>(a, s, grid);
-  if (mode == kBackward) return run<Cfg<P, C, H, NH, kBackward>>(a, s, grid);
-  return run<Cfg<P, C, H, NH, kTrain>>(a, s, grid);
+  if (mode == kForward) return run<Cfg<P, C, H, NH, kForward, VD>>(a, s, grid);
+  if (mode == kBackward) return run<Cfg<P, C, H, NH, kBackward, VD>>(a, s, grid);
+  return run<Cfg<P, C, H, NH, kTrain, VD>>(a, s, grid);
 }
 
-template <int P, int C, int H, int NH>
+template <int P, int C, int H, int NH, int VD>
 hipError_t run_mlp(const float* params, const float* X, int64_t n, float* out, hipStream_t s) {
-  using CF = Cfg<P, C, H, NH, kForward>;
+  using CF = Cfg<P, C, H, NH, kForward, VD>;
   const auto kern = k_mlp_rows<CF>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, CF::LDS_BYTES);
@@ -958,8 +996,9 @@ hipError_t run_mlp(const float* params, const float* X, int64_t n, float* out, h
   return hipGetLastError();
 }
 
-// Supported decoder shapes (C, H, hidden layers).
-#define SVLF_SHAPES(X) X(8, 32, 2) X(16, 64, 3) X(32, 64, 3)
+// Supported decoder shapes (C, H, hidden layers, view-direction input).
+#define SVLF_SHAPES(X) \
+  X(8, 32, 2, 0) X(16, 64, 3, 0) X(32, 64, 3, 0) X(8, 32, 2, 1) X(32, 64, 3, 1)
 
 }  // namespace
 
@@ -968,22 +1007,25 @@ int shade_grid_limit() { return 1024; }
 hipError_t launch_shade(const ShadeArgs& a, int mode, hipStream_t s, int* grid_used) {
   *grid_used = 0;
   const int P = a.precision == SVLF_BF16 ? 1 : 0;
-#define SVLF_CASE(C_, H_, NH_)                                                         \
-  if (a.C == C_ && a.H == H_ && a.n_hidden == NH_)                                     \
-    return P ? run_mode<1, C_, H_, NH_>(a, mode, s, grid_used)                         \
-             : run_mode<0, C_, H_, NH_>(a, mode, s, grid_used);
+  const int vd = a.viewdir ? 1 : 0;
+#define SVLF_CASE(C_, H_, NH_, VD_)                                                    \
+  if (a.C == C_ && a.H == H_ && a.n_hidden == NH_ && vd == VD_)                        \
+    return P ? run_mode<1, C_, H_, NH_, VD_>(a, mode, s, grid_used)                    \
+             : run_mode<0, C_, H_, NH_, VD_>(a, mode, s, grid_used);
   SVLF_SHAPES(SVLF_CASE)
 #undef SVLF_CASE
   return hipErrorNotSupported;
 }
 
-hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, int precision,
-                              const float* X, int64_t n, float* out, hipStream_t s) {
+hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, int viewdir,
+                              int precision, const float* X, int64_t n, float* out,
+                              hipStream_t s) {
   const int P = precision == SVLF_BF16 ? 1 : 0;
-#define SVLF_CASE(C_, H_, NH_)                                                         \
-  if (C == C_ && H == H_ && n_hidden == NH_)                                           \
-    return P ? run_mlp<1, C_, H_, NH_>(params, X, n, out, s)                           \
-             : run_mlp<0, C_, H_, NH_>(params, X, n, out, s);
+  const int vd = viewdir ? 1 : 0;
+#define SVLF_CASE(C_, H_, NH_, VD_)                                                    \
+  if (C == C_ && H == H_ && n_hidden == NH_ && vd == VD_)                              \
+    return P ? run_mlp<1, C_, H_, NH_, VD_>(params, X, n, out, s)                      \
+             : run_mlp<0, C_, H_, NH_, VD_>(params, X, n, out, s);
   SVLF_SHAPES(SVLF_CASE)
 #undef SVLF_CASE
   return hipErrorNotSupported;

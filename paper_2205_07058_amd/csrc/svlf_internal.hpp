@@ -51,8 +51,7 @@ hipError_t launch_trace_public(const svlf_octree& oct, const float* o, const flo
                                int64_t n, int K, int32_t* leaf, float* tin, float* tout,
                                int32_t* cnt, hipStream_t s);
 hipError_t launch_trace_internal(const SceneTable& tab, const float* o, const float* d,
-                                 int K, HitRec* hits, int32_t* cnt, unsigned long long* counter,
-                                 hipStream_t s);
+                                 int K, HitRec* hits, int32_t* cnt, hipStream_t s);
 
 struct ShadeArgs {
   SceneTable tab;
@@ -63,9 +62,10 @@ struct ShadeArgs {
   int32_t K;
   int32_t tau_mode;
   int32_t precision;
-  int32_t C;
+  int32_t C;              // features per vertex
   int32_t H;
   int32_t n_hidden;
+  int32_t viewdir;        // decoder input [psi | d] (width C + 3)
   const float* params;
   // forward outputs
   float* rgb;
@@ -102,8 +102,12 @@ hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float 
                        hipStream_t s);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t s);
 hipError_t launch_fill(float* dst, float v, int64_t n, hipStream_t s);
-hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, int precision,
-                              const float* X, int64_t n, float* out, hipStream_t s);
+hipError_t launch_lazy_adam(float* p, float* g, float* m, float* v, int64_t n_rows, int row_len,
+                            float lr, float b1, float b2, float eps, float bc1, float bc2,
+                            uint16_t* bf16, int zero, hipStream_t s);
+hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, int viewdir,
+                              int precision, const float* X, int64_t n, float* out,
+                              hipStream_t s);
 
 // Host octree build (octree_build.cpp).
 struct HostOctree {

@@ -142,62 +142,42 @@ __device__ __forceinline__ bool root_hit(const Ray& r) {
   return tin < tout;
 }
 
-// Resumable front-to-back walk of one ray (one lane).  step() performs one
-// node expansion, push or pop; leaves below an expanded node are emitted in
-// order through emit(slot, leaf, t_in, t_out, ijk) until K leaves were found.
-// The per-level stack lives in LDS (`stk`, this lane's entry of level 0 of an
-// array laid out [level][stride]).
-struct Walker {
-  Ray ray;
-  const svlf_node* nodes;
-  int depth;
-  int level;
-  uint32_t ci, cj, ck;
-  svlf_node nd;
-  uint32_t rem;
-  bool expand;
-  int count;
-
-  // Starts a ray; returns false if it cannot hit anything.
-  __device__ __forceinline__ bool start(const Ray& r, const svlf_node* __restrict__ n, int d) {
-    ray = r;
-    nodes = n;
-    depth = d;
-    count = 0;
-    if (n == nullptr || !r.valid || !root_hit(r)) return false;
-    level = 0;
-    ci = cj = ck = 0;
-    nd = n[0];
-    rem = 0;
-    expand = true;
-    return true;
-  }
-
-  // One step; returns true when the ray is finished (count is final).
-  template <class Emit>
-  __device__ __forceinline__ bool step(int K, uint2* stk, int stride, Emit& emit) {
+// Walks the octree front to back; calls emit(slot, leaf, t_in, t_out, ijk)
+// for the first K hit leaves.  `stk` points at this lane's entry of level 0
+// of an LDS array laid out [level][stride].  Returns the number of hits.
+template <class Emit>
+__device__ __forceinline__ int traverse(const Ray& r, const svlf_node* __restrict__ nodes,
+                                        int depth, int K, uint2* stk, int stride, Emit emit) {
+  if (!r.valid || !root_hit(r)) return 0;
+  int count = 0;
+  int level = 0;
+  uint32_t ci = 0, cj = 0, ck = 0;
+  svlf_node nd = nodes[0];
+  uint32_t rem = 0;
+  bool expand = true;
+  while (true) {
     if (expand) {
       expand = false;
-      const Kids kd = node_kids(ray, level, ci, cj, ck);
-      rem = to_order(kid_hits(kd, nd.mask), ray.oct);
+      const Kids kd = node_kids(r, level, ci, cj, ck);
+      rem = to_order(kid_hits(kd, nd.mask), r.oct);
       if (level == depth - 1) {
         // children are leaves: emit them in order
         while (rem) {
           const uint32_t i = __builtin_ctz(rem);
           rem &= rem - 1;
-          const uint32_t c = i ^ ray.oct;
+          const uint32_t c = i ^ r.oct;
           float tin, tout;
           kid_interval(kd, c, tin, tout);
           const int32_t leaf = nd.child + __builtin_popcount(nd.mask & ((1u << c) - 1u));
-          const uint32_t li = 2 * ci + (c & 1), lj = 2 * cj + ((c >> 1) & 1), lk = 2 * ck + (c >> 2);
+          const uint32_t li = 2 * ci + (c & 1), lj = 2 * cj + ((c >> 1) & 1),
+                         lk = 2 * ck + (c >> 2);
           emit(count, leaf, tin, tout, li | (lj << 10) | (lk << 20));
-          if (++count == K) return true;
+          if (++count == K) return count;
         }
       }
-      return false;
     }
     if (rem == 0) {
-      if (level == 0) return true;
+      if (level == 0) break;
       --level;
       ci >>= 1;
       cj >>= 1;
@@ -206,11 +186,11 @@ struct Walker {
       nd.child = static_cast<int32_t>(e.x);
       nd.mask = e.y & 0xFFu;
       rem = e.y >> 8;
-      return false;
+      continue;
     }
     const uint32_t i = __builtin_ctz(rem);
     rem &= rem - 1;
-    const uint32_t c = i ^ ray.oct;
+    const uint32_t c = i ^ r.oct;
     const int32_t idx = nd.child + __builtin_popcount(nd.mask & ((1u << c) - 1u));
     stk[level * stride] = make_uint2(static_cast<uint32_t>(nd.child), nd.mask | (rem << 8));
     ++level;
@@ -219,8 +199,8 @@ struct Walker {
     ck = 2 * ck + (c >> 2);
     nd = nodes[idx];
     expand = true;
-    return false;
   }
-};
+  return count;
+}
 
 }  // namespace svlf

@@ -43,6 +43,59 @@ __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ p, float*
   }
 }
 
+// Lazy (row-sparse) Adam: rows of `L4` float4 groups (row length 4*L4
+// floats); a row is updated, and its gradient cleared, only if some entry of
+// its gradient is nonzero; other rows (their moments included) are left
+// untouched.  Bias corrections use the global step.  Each row is handled by
+// L4 consecutive lanes of one wave, 64/L4 rows per wave per iteration.
+__global__ __launch_bounds__(kThreads) void k_lazy_adam(float4* __restrict__ p,
+                                                        float4* __restrict__ g,
+                                                        float4* __restrict__ m,
+                                                        float4* __restrict__ v, int64_t n_rows,
+                                                        int L4, float lr, float b1, float b2,
+                                                        float eps, float bc1, float bc2,
+                                                        uint2* __restrict__ bf, int zero) {
+  const int lane = threadIdx.x & 63;
+  const int rpw = 64 / L4;
+  const int grp = lane / L4;
+  const int sub = lane - grp * L4;
+  const unsigned long long gmask =
+      (L4 == 64 ? ~0ull : ((1ull << L4) - 1ull)) << (grp < rpw ? grp * L4 : 0);
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) >> 6;
+  const int64_t n_waves = (static_cast<int64_t>(gridDim.x) * kThreads) >> 6;
+  for (int64_t r0 = wave * rpw; r0 < n_rows; r0 += n_waves * rpw) {
+    const int64_t r = r0 + grp;
+    const bool ok = grp < rpw && r < n_rows;
+    const int64_t i = r * L4 + sub;
+    float4 gi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (ok) gi = g[i];
+    const bool nz = ok && (gi.x != 0.0f || gi.y != 0.0f || gi.z != 0.0f || gi.w != 0.0f);
+    const unsigned long long any = __ballot(nz);
+    if (!ok || (any & gmask) == 0ull) continue;
+    float4 mi = m[i], vi = v[i], pi = p[i];
+    float* mf = &mi.x;
+    float* vf = &vi.x;
+    float* pf = &pi.x;
+    const float* gf = &gi.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mf[c] = b1 * mf[c] + (1.0f - b1) * gf[c];
+      vf[c] = b2 * vf[c] + (1.0f - b2) * gf[c] * gf[c];
+      pf[c] = pf[c] - lr * (mf[c] / bc1) / (sqrtf(vf[c] / bc2) + eps);
+    }
+    m[i] = mi;
+    v[i] = vi;
+    p[i] = pi;
+    if (bf) {
+      uint2 b;
+      b.x = static_cast<uint32_t>(bf16_bits(pi.x)) | (static_cast<uint32_t>(bf16_bits(pi.y)) << 16);
+      b.y = static_cast<uint32_t>(bf16_bits(pi.z)) | (static_cast<uint32_t>(bf16_bits(pi.w)) << 16);
+      bf[i] = b;
+    }
+    if (zero) g[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_to_bf16(const float* __restrict__ s,
                                                       uint16_t* __restrict__ d, int64_t n) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
@@ -82,6 +135,21 @@ hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float 
                        hipStream_t s) {
   hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(kThreads), 0, s, p, g, m, v, n, lr, b1, b2,
                      eps, bc1, bc2, bf16, zero);
+  return hipGetLastError();
+}
+
+hipError_t launch_lazy_adam(float* p, float* g, float* m, float* v, int64_t n_rows, int row_len,
+                            float lr, float b1, float b2, float eps, float bc1, float bc2,
+                            uint16_t* bf16, int zero, hipStream_t s) {
+  const int L4 = row_len / 4;
+  const int64_t rows_per_block = (kThreads / 64) * (64 / L4);
+  int64_t blocks = (n_rows + rows_per_block - 1) / rows_per_block;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_lazy_adam, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
+                     reinterpret_cast<float4*>(p), reinterpret_cast<float4*>(g),
+                     reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n_rows, L4, lr,
+                     b1, b2, eps, bc1, bc2, reinterpret_cast<uint2*>(bf16), zero);
   return hipGetLastError();
 }
 

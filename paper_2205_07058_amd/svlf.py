@@ -29,6 +29,7 @@ TAU_MODES = {"voxel": 0, "direct": 1, "world": 2}
 PRECISIONS = {"fp32": 0, "bf16": 1}
 FLAG_TRACE_ONLY = 1
 FLAG_REUSE_HITS = 2
+FLAG_VIEWDIR = 4
 
 
 class Node(ct.Structure):
@@ -87,6 +88,9 @@ _SIGS = {
     "svlf_adam_step": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float,
                         ct.c_float, ct.c_float, ct.c_float, ct.c_int64, ct.c_void_p, ct.c_int32,
                         ct.c_void_p], ct.c_int),
+    "svlf_lazy_adam_step": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
+                             ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_int64,
+                             ct.c_void_p, ct.c_int32, ct.c_void_p], ct.c_int),
     "svlf_to_bf16": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_fill": ([ct.c_void_p, ct.c_float, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_mlp_forward": ([ct.POINTER(Mlp), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_int64,
@@ -427,6 +431,25 @@ def adam_step(param, grad, m, v, lr, beta1, beta2, eps, step_t, bf16_out=None, z
                                  _ptr(bf16_out, torch.int16, tuple(param.shape), "bf16_out",
                                       allow_none=True),
                                  1 if zero_grad else 0, _stream()))
+
+
+def lazy_adam_step(param, grad, m, v, lr, beta1, beta2, eps, step_t, bf16_out=None,
+                   zero_grad=True):
+    """Row-sparse Adam over a 2-D table [rows][row_len] (rows whose gradient
+    is all zero are left untouched)."""
+    torch = _torch()
+    if param.dim() != 2:
+        raise ValueError("lazy_adam_step: param must be 2-D [rows][row_len]")
+    rows, row_len = param.shape
+    for t, nm in ((grad, "grad"), (m, "m"), (v, "v")):
+        _ptr(t, torch.float32, tuple(param.shape), nm)
+    _check("svlf_lazy_adam_step",
+           load().svlf_lazy_adam_step(_ptr(param, torch.float32, name="param"), _ptr(grad),
+                                      _ptr(m), _ptr(v), rows, row_len, lr, beta1, beta2, eps,
+                                      int(step_t),
+                                      _ptr(bf16_out, torch.int16, tuple(param.shape), "bf16_out",
+                                           allow_none=True),
+                                      1 if zero_grad else 0, _stream()))
 
 
 def to_bf16(src, dst):

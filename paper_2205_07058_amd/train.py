@@ -2,7 +2,8 @@
 
 One step = svlf_train_step (traversal, gather, decoder, Eq. 3, MSE + L1 loss
 and the hand-written backward) followed by svlf_adam_step on the features
-(refreshing their BF16 copy in the same pass) and on the decoder parameters.
+(refreshing their BF16 copy in the same pass; dense, or lazy over the feature
+rows the batch touched) and on the decoder parameters.
 The paper trains with Adam at learning rate 1e-3 (section 4.5).
 """
 
@@ -16,16 +17,20 @@ from . import svlf
 class Trainer:
     def __init__(self, scene: "svlf.DeviceScene", params: torch.Tensor, widths, K,
                  precision="bf16", tau_mode="voxel", lr_features=1e-3, lr_params=1e-3,
-                 lambda_depth=0.1, betas=(0.9, 0.999), eps=1e-8):
+                 lambda_depth=0.1, betas=(0.9, 0.999), eps=1e-8, feature_optimizer="adam",
+                 viewdir=False):
         self.scene = scene
         self.params = params
         self.widths = tuple(widths)
-        self.opts = svlf.make_opts(K, tau_mode, precision)
+        self.opts = svlf.make_opts(K, tau_mode, precision, svlf.FLAG_VIEWDIR if viewdir else 0)
         self.precision = precision
         self.lr_f, self.lr_p = lr_features, lr_params
         self.lam = lambda_depth
         self.b1, self.b2 = betas
         self.eps = eps
+        if feature_optimizer not in ("adam", "lazy_adam"):
+            raise ValueError("feature_optimizer must be 'adam' or 'lazy_adam'")
+        self.feature_optimizer = feature_optimizer
         f = scene.features
         self.gF = torch.zeros_like(f)
         self.mF = torch.zeros_like(f)
@@ -52,8 +57,9 @@ class Trainer:
     def optimizer_step(self):
         self.t += 1
         bf = self.scene.features_bf16 if self.precision == "bf16" else None
-        svlf.adam_step(self.scene.features, self.gF, self.mF, self.vF, self.lr_f, self.b1, self.b2,
-                       self.eps, self.t, bf16_out=bf, zero_grad=True)
+        upd = svlf.lazy_adam_step if self.feature_optimizer == "lazy_adam" else svlf.adam_step
+        upd(self.scene.features, self.gF, self.mF, self.vF, self.lr_f, self.b1, self.b2,
+            self.eps, self.t, bf16_out=bf, zero_grad=True)
         svlf.adam_step(self.params, self.gp, self.mp, self.vp, self.lr_p, self.b1, self.b2,
                        self.eps, self.t, zero_grad=True)
 

@@ -69,9 +69,11 @@ def psnr(a, b):
 class Case:
     """A scene + decoder on the device and in the oracle."""
 
-    def __init__(self, svlf, leaf_ijk, depth, features, params, widths, K, tau_mode="voxel"):
+    def __init__(self, svlf, leaf_ijk, depth, features, params, widths, K, tau_mode="voxel",
+                 viewdir=False):
         import torch
         self.svlf = svlf
+        self.viewdir = viewdir
         self.depth = depth
         self.widths = tuple(widths)
         self.K = K
@@ -83,16 +85,23 @@ class Case:
         self.params = torch.from_numpy(self.p).cuda()
 
     @classmethod
-    def from_workload(cls, svlf, w, feat_scale=1.0, sigma_bias=None, tau_mode="voxel"):
+    def from_workload(cls, svlf, w, feat_scale=1.0, sigma_bias=None, tau_mode="voxel",
+                      viewdir=False):
         sc = w.scene()
         F = w.features() * np.float32(feat_scale)
+        widths = tuple(w.widths)
         p = w.params().copy()
+        if viewdir:
+            from synth.configs import xavier_params
+            widths = (widths[0] + 3,) + widths[1:]
+            p = xavier_params(np.random.default_rng(len(widths) + widths[0]), widths)
         if sigma_bias is not None:
             p[-1] = sigma_bias
-        return cls(svlf, sc.leaf_ijk, sc.depth, F, p, w.widths, w.K, tau_mode)
+        return cls(svlf, sc.leaf_ijk, sc.depth, F, p, widths, w.K, tau_mode, viewdir)
 
     def opts(self, precision="fp32"):
-        return self.svlf.make_opts(self.K, self.tau_mode, precision)
+        return self.svlf.make_opts(self.K, self.tau_mode, precision,
+                                   self.svlf.FLAG_VIEWDIR if self.viewdir else 0)
 
     def rays(self, o, d):
         import torch
@@ -125,4 +134,4 @@ class Case:
     def oracle(self, o, d, bf16=False):
         hits = oracle_trace(self.oc, o, d, self.K)
         return oracle_render(self.oc, self.F, self.p, self.widths, o, d, hits,
-                             tau_mode=self.tau_mode, bf16=bf16)
+                             tau_mode=self.tau_mode, bf16=bf16, viewdir=self.viewdir)

@@ -101,6 +101,16 @@ def test_render_validation(lib):
         assert args(sc, 1, offs, ct.byref(mm), ct.byref(opts), None, 0) == code, widths
     mm = _mlp(null_params=True)
     assert args(sc, 1, offs, ct.byref(mm), ct.byref(opts), None, 0) == svlf.E_INVAL
+    # view-direction input: widths[0] = C + 3 for the two supported decoders
+    vopts = svlf.make_opts(8, flags=svlf.FLAG_VIEWDIR)
+    for widths in ((8, 32, 32, 4), (19, 64, 64, 64, 4), (11, 64, 64, 64, 4), (35, 32, 32, 4)):
+        mm = _mlp(widths)
+        assert args(sc, 1, offs, ct.byref(mm), ct.byref(vopts), None, 0) == svlf.E_UNSUPPORTED, widths
+    for widths in ((11, 32, 32, 4), (35, 64, 64, 64, 4)):
+        mm = _mlp(widths)
+        assert lib.svlf_workspace_bytes(ct.byref(mm), ct.byref(vopts), 100) > 0, widths
+        # accepted shapes fail later, at the (missing) workspace
+        assert args(sc, 1, offs, ct.byref(mm), ct.byref(vopts), None, 0) == svlf.E_WORKSPACE, widths
     # workspace too small (empty scene: only the workspace check can fail)
     ws_need = lib.svlf_workspace_bytes(ct.byref(m), ct.byref(opts), 100)
     assert ws_need > 100 * 8 * 16
@@ -125,6 +135,16 @@ def test_adam_and_util_validation(lib):
     assert lib.svlf_adam_step(None, None, None, None, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None, 1, None) == svlf.E_RANGE
     assert lib.svlf_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.E_INVAL
     assert lib.svlf_adam_step(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.OK
+    la = lib.svlf_lazy_adam_step
+    assert la(None, None, None, None, 10, 6, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.E_UNSUPPORTED
+    assert la(None, None, None, None, 10, 260, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.E_UNSUPPORTED
+    assert la(None, None, None, None, 10, 32, 1e-3, 0.9, 0.999, 1e-8, 0, None, 1, None) == svlf.E_RANGE
+    assert la(None, None, None, None, 10, 32, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.E_INVAL
+    assert la(None, None, None, None, -1, 32, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.E_INVAL
+    assert la(None, None, None, None, 0, 32, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.OK
+    # misaligned pointers are rejected on the host (never dereferenced)
+    assert la(16, 32, 48, 68, 10, 32, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, None) == svlf.E_INVAL
+    assert la(16, 32, 48, 64, 10, 32, 1e-3, 0.9, 0.999, 1e-8, 1, 4, 1, None) == svlf.E_INVAL
     assert lib.svlf_to_bf16(None, None, 5, None) == svlf.E_INVAL
     assert lib.svlf_fill(None, 0.0, -1, None) == svlf.E_INVAL
 

@@ -146,6 +146,51 @@ def test_single_voxel_closed_form(tau_mode):
     np.testing.assert_allclose(acc[0], 1.0 - np.exp(-tau), rtol=1e-12)
 
 
+def test_viewdir_closed_form():
+    """View-direction input: a decoder whose colour channel 0 is
+    sigmoid(relu(d_x)) and whose sigma is a constant gives, for two rays
+    crossing the same voxel in different directions, colours that differ
+    exactly as the closed form says; zero weights on d reproduce the render
+    without the direction input."""
+    depth = 2
+    oc = Octree([[1, 2, 1]], depth)
+    C = 4
+    widths = (C + 3, 4, 4)
+    F = np.tile([0.3, -0.1, 0.2, 0.5], (oc.n_vertices, 1))
+    p = np.zeros(param_count(widths))
+    W1 = p[:4 * 7].reshape(4, 7)
+    W1[0, C + 0] = 1.0                            # hidden 0 = relu(d_x)
+    off = 4 * 7 + 4
+    W2 = p[off:off + 16].reshape(4, 4)
+    W2[0, 0] = 1.0                                # o_0 = hidden 0
+    p[off + 16:off + 20] = [0.0, 0.0, 0.0, 2.0]   # sigma = 2
+    ctr = np.array([-0.25, 0.25, -0.25])
+    dirs = np.array([[0.6, 0.8, 0.0], [-0.28, 0.96, 0.0]], np.float32)
+    o = (ctr - 3.0 * dirs).astype(np.float32)
+    _, (rgb, dep, acc, st) = _render_one(oc, F, p, widths, o, dirs, viewdir=True)
+    a = acc
+    assert np.all(a > 0)
+    dx = dirs[:, 0].astype(np.float64)
+    np.testing.assert_allclose(rgb[:, 0], a / (1.0 + np.exp(-np.maximum(dx, 0.0))), rtol=1e-12)
+    np.testing.assert_allclose(rgb[:, 1], 0.5 * a, rtol=1e-12)
+    assert rgb[0, 0] != rgb[1, 0]
+    # the same decoder with the direction weights removed is the plain render
+    widths0 = (C, 4, 4)
+    p0 = np.concatenate([np.zeros(4 * 4 + 4), p[off:]])
+    _, (rgb0, dep0, acc0, _) = _render_one(oc, F, p0, widths0, o, dirs)
+    p_vd = p.copy()
+    W1[0, C] = 0.0
+    _, (rgb1, dep1, acc1, _) = _render_one(oc, F, p, widths, o, dirs, viewdir=True)
+    np.testing.assert_array_equal(rgb1, rgb0)
+    np.testing.assert_array_equal(dep1, dep0)
+    np.testing.assert_array_equal(acc1, acc0)
+    # the direction takes no gradient and the feature gradient keeps C columns
+    gF, gp = render_backward(st, np.ones((2, 3)), np.zeros(2))
+    assert gF.shape == (oc.n_vertices, C)
+    with pytest.raises(ValueError):
+        _render_one(oc, F, p_vd, widths, o, dirs)     # width C + 3 without viewdir
+
+
 def test_telescoping_constant_decoder():
     """Constant decoder: acc = 1 - exp(-sigma sum(dt)/h), rgb = c acc."""
     depth = 3
@@ -203,12 +248,15 @@ def test_compositing_invariants():
 
 # ------------------------------------------------------------ gradients
 
-def _fd_setup(seed, tau_mode="voxel", bf16=False):
+def _fd_setup(seed, tau_mode="voxel", bf16=False, viewdir=False):
     w = tiny_workload(seed, 3, 8, (8, 16, 16, 4), 4, n_obj=2)
     sc = w.scene()
     oc = Octree(sc.leaf_ijk, sc.depth)
     F = w.features().astype(np.float64)
     p = w.params().astype(np.float64)
+    if viewdir:
+        w.widths = (11, 16, 16, 4)
+        p = xavier_params(np.random.default_rng(seed + 100), w.widths).astype(np.float64)
     p[-1] = 0.5                                   # sigma mostly positive
     rng = np.random.default_rng(seed)
     o, d = random_rays(rng, 64, inside_frac=0.1, axis_frac=0.0)
@@ -218,8 +266,8 @@ def _fd_setup(seed, tau_mode="voxel", bf16=False):
     return oc, F, p, w.widths, o, d, hits, rgb_t, dep_t
 
 
-def _loss_at(oc, F, p, widths, o, d, hits, rgb_t, dep_t, tau_mode):
-    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits, tau_mode=tau_mode)
+def _loss_at(oc, F, p, widths, o, d, hits, rgb_t, dep_t, tau_mode, viewdir=False):
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits, tau_mode=tau_mode, viewdir=viewdir)
     return loss(rgb, dep, rgb_t, dep_t)[0], st, rgb, dep
 
 
@@ -230,18 +278,18 @@ def _pattern(st, dep, dep_t):
                            st.out[:, 3] > 0, dep - dep_t > 0])
 
 
-@pytest.mark.parametrize("tau_mode", ["voxel", "world"])
-def test_gradients_against_central_differences(tau_mode):
-    oc, F, p, widths, o, d, hits, rgb_t, dep_t = _fd_setup(12, tau_mode)
-    L0, st, rgb, dep = _loss_at(oc, F, p, widths, o, d, hits, rgb_t, dep_t, tau_mode)
+@pytest.mark.parametrize("tau_mode,viewdir", [("voxel", False), ("world", False), ("voxel", True)])
+def test_gradients_against_central_differences(tau_mode, viewdir):
+    oc, F, p, widths, o, d, hits, rgb_t, dep_t = _fd_setup(12, tau_mode, viewdir=viewdir)
+    L0, st, rgb, dep = _loss_at(oc, F, p, widths, o, d, hits, rgb_t, dep_t, tau_mode, viewdir)
     base = _pattern(st, dep, dep_t)
     _, g_rgb, g_dep = loss(rgb, dep, rgb_t, dep_t)
     gF, gp = render_backward(st, g_rgb, g_dep)
     assert np.count_nonzero(gF) > 0
 
     def fd_of(Fx_p, Fx_m, px_p, px_m, eps):
-        Lp, stp, _, dp = _loss_at(oc, Fx_p, px_p, widths, o, d, hits, rgb_t, dep_t, tau_mode)
-        Lm, stm, _, dm = _loss_at(oc, Fx_m, px_m, widths, o, d, hits, rgb_t, dep_t, tau_mode)
+        Lp, stp, _, dp = _loss_at(oc, Fx_p, px_p, widths, o, d, hits, rgb_t, dep_t, tau_mode, viewdir)
+        Lm, stm, _, dm = _loss_at(oc, Fx_m, px_m, widths, o, d, hits, rgb_t, dep_t, tau_mode, viewdir)
         # an evaluation that straddles a kink is not a derivative: skip it
         if not (np.array_equal(_pattern(stp, dp, dep_t), base)
                 and np.array_equal(_pattern(stm, dm, dep_t), base)):
