@@ -17,10 +17,14 @@ What it computes (SVLF, arxiv 2205.07058, section 4):
   alpha compositing (Eq. 3), in FP64, with an optional BF16-rounding mode;
   the hand-derived backward of all of it; the loss and its gradient.
 * ``optim``   -- Adam (section 4.5), dense and restricted to touched rows.
+* ``lightfield`` -- the paper's two-decoder voxel light-field function
+  (sections 4.1-4.3: bounding-sphere ray parameterisation, density decoder
+  on the features at the entry and exit points giving tau and eta, colour
+  decoder on the features at the surface point, Eq. 3) and its backward.
 
 Every function states the passage it follows.  Parity status: every function
 is pinned by the ``-m "not gpu"`` tests (brute force, exact rationals, closed
 forms, invariants and finite differences); none is "parity unpinned".
 """
 
-from . import octree, trace, render, optim  # noqa: F401
+from . import octree, trace, render, optim, lightfield  # noqa: F401

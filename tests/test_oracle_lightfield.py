@@ -1,0 +1,331 @@
+"""Pins for the two-decoder light-field oracle (SVLF sections 4.1-4.3):
+closed forms of the bounding-sphere ray parameterisation, of where each
+decoder reads its features (x1, x2, the surface point between them), of
+the surface-point depth, finite differences of the loss through every
+parameter and feature (including the path eta -> x_s -> psi), and
+conservation identities of the feature gradients."""
+
+import numpy as np
+import pytest
+
+from oracle.lightfield import (n_params, render_lf, render_lf_backward, sphere_param, widths_of)
+from oracle.octree import Octree
+from oracle.render import loss
+from oracle.trace import trace_hits
+from synth.configs import tiny_workload, xavier_params
+from tests.helpers import random_rays
+
+
+def _layers_flat(layers):
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers])
+
+
+def _zeros(widths):
+    return [(np.zeros((b, a)), np.zeros(b)) for a, b in zip(widths[:-1], widths[1:])]
+
+
+def _one_voxel():
+    depth = 2
+    oc = Octree([[1, 2, 1]], depth)
+    h = 0.5
+    lo = np.array([-0.5, 0.0, -0.5])
+    return oc, h, lo
+
+
+def _vertex_pos(oc, h):
+    """World position of every vertex (rank of the Morton code of the
+    (L+1)-bit corner lattice; corners of leaf 0 in corner order)."""
+    pos = np.zeros((oc.n_vertices, 3))
+    for j in range(8):
+        v = oc.leaf_corners[0, j]
+        off = np.array([j & 1, (j >> 1) & 1, j >> 2])
+        pos[v] = -1.0 + (oc.leaf_ijk[0] + off) * h
+    return pos
+
+
+# ------------------------------------------------------------ ray parameterisation
+
+def test_sphere_param_closed_forms():
+    lo = np.array([[0.0, 0.0, 0.0]])
+    h = 0.5
+    c = lo + 0.25
+    # axis ray through the centre: the sphere points are c -/+ R e_x
+    o = c + np.array([[-3.0, 0.0, 0.0]])
+    r, ta, tb = sphere_param(o, np.array([[1.0, 0.0, 0.0]]), lo, h)
+    np.testing.assert_allclose(r, [[-1, 0, 0, 1, 0, 0]], atol=1e-15)
+    R = h * np.sqrt(3) / 2
+    np.testing.assert_allclose([ta[0], tb[0]], [3.0 - R, 3.0 + R], rtol=1e-15)
+    # main diagonal through the centre, unnormalised direction
+    s = 1.0 / np.sqrt(3)
+    r, ta, tb = sphere_param(c - 2.0, np.array([[1.0, 1.0, 1.0]]), lo, h)
+    np.testing.assert_allclose(r, [[-s, -s, -s, s, s, s]], atol=1e-15)
+    # off-centre ray: both points on the sphere, unit vectors, symmetric about
+    # the point of closest approach
+    rng = np.random.default_rng(0)
+    o = c + rng.uniform(-0.2, 0.2, (50, 3)) - np.array([2.0, 0, 0])
+    d = np.column_stack([np.ones(50), rng.uniform(-0.05, 0.05, (50, 2))])
+    r, ta, tb = sphere_param(o, d, np.repeat(lo, 50, 0), h)
+    np.testing.assert_allclose(np.linalg.norm(r[:, :3], axis=1), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(np.linalg.norm(r[:, 3:], axis=1), 1.0, rtol=1e-14)
+    p1 = o + ta[:, None] * d
+    p2 = o + tb[:, None] * d
+    np.testing.assert_allclose(np.linalg.norm(p1 - c, axis=1), R, rtol=1e-12)
+    np.testing.assert_allclose(np.linalg.norm(p2 - c, axis=1), R, rtol=1e-12)
+    tmid = 0.5 * (ta + tb)
+    closest = -np.sum((o - c) * d, axis=1) / np.sum(d * d, axis=1)
+    np.testing.assert_allclose(tmid, closest, rtol=1e-12)
+
+
+# ------------------------------------------------------------ closed-form renders
+
+def _axis_ray(h, lo, y_frac=0.3, z_frac=0.6):
+    """+x ray crossing the voxel at fractional (y, z); t_in = 2, t_out = 2 + h."""
+    o = np.array([[lo[0] - 2.0, lo[1] + y_frac * h, lo[2] + z_frac * h]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0]], np.float32)
+    return o, d
+
+
+@pytest.mark.parametrize("beta", [-1.3, 0.0, 2.2])
+def test_colour_read_at_surface_point(beta):
+    """Density decoder = constants (sigma = s, eta = sigmoid(beta)); colour
+    decoder = identity on the colour features; colour features a linear
+    field (trilinear interpolation reproduces it exactly) -> the colour is
+    sigmoid of the field at x_s = eta x1 + (1 - eta) x2."""
+    oc, h, lo = _one_voxel()
+    dec = (2, 3, 4, 1, 1)
+    wt, wc = widths_of(dec)
+    lt, lc = _zeros(wt), _zeros(wc)
+    s = 0.7
+    lt[-1][1][:] = [s, beta]                      # output biases of F_T
+    W0, b0 = lc[0]
+    W0[0, 0] = W0[1, 1] = W0[2, 2] = 1.0          # hidden k = relu(z_C,k + 10)
+    b0[:3] = 10.0
+    W1, b1 = lc[1]
+    W1[0, 0] = W1[1, 1] = W1[2, 2] = 1.0          # o_k = hidden_k - 10
+    b1[:] = -10.0
+    p = np.concatenate([_layers_flat(lt), _layers_flat(lc)])
+    assert p.size == n_params(dec)
+    A = np.array([[0.8, -0.3, 0.5], [-0.2, 0.9, 0.1], [0.4, 0.4, -0.7]])
+    pos = _vertex_pos(oc, h)
+    F = np.zeros((oc.n_vertices, 5))
+    F[:, :2] = 3.0                                 # Z_T: irrelevant here
+    F[:, 2:] = pos @ A.T + 0.1                     # Z_C: linear field
+    o, d = _axis_ray(h, lo)
+    hits = trace_hits(oc, o, d, 4)
+    rgb, dep, acc, st = render_lf(oc, F, p, dec, o, d, hits)
+    t_in, t_out = 2.0, 2.0 + h
+    np.testing.assert_allclose([hits[1][0, 0], hits[2][0, 0]], [t_in, t_out])
+    eta = 1.0 / (1.0 + np.exp(-beta))
+    x1 = o[0].astype(np.float64) + t_in * d[0]
+    x2 = o[0].astype(np.float64) + t_out * d[0]
+    xs = eta * x1 + (1.0 - eta) * x2
+    alpha = 1.0 - np.exp(-s)                       # "direct": tau = sigma
+    c = 1.0 / (1.0 + np.exp(-(A @ xs + 0.1)))
+    np.testing.assert_allclose(rgb[0], alpha * c, rtol=1e-12)
+    np.testing.assert_allclose(acc[0], alpha, rtol=1e-12)
+    np.testing.assert_allclose(dep[0], alpha * (eta * t_in + (1.0 - eta) * t_out), rtol=1e-12)
+
+
+def test_density_reads_entry_and_exit_features():
+    """sigma from psi(x1; Z_T) channel 0, eta from psi(x2; Z_T) channel 1, with
+    Z_T a linear field: closed forms for opacity and depth."""
+    oc, h, lo = _one_voxel()
+    dec = (2, 1, 4, 1, 1)
+    wt, wc = widths_of(dec)
+    lt, lc = _zeros(wt), _zeros(wc)
+    W0, b0 = lt[0]
+    W0[0, 0] = 1.0                                 # hidden 0 = relu(psi(x1)_0 + 5)
+    b0[0] = 5.0
+    W0[1, 2 + 1] = 1.0                             # hidden 1 = relu(psi(x2)_1 + 5)
+    b0[1] = 5.0
+    W1, b1 = lt[1]
+    W1[0, 0] = 1.0
+    W1[1, 1] = 1.0
+    b1[:] = [-5.0, -5.0]
+    p = np.concatenate([_layers_flat(lt), _layers_flat(lc)])
+    pos = _vertex_pos(oc, h)
+    F = np.zeros((oc.n_vertices, 3))
+    F[:, 0] = pos @ [1.5, 0.2, -0.4] + 1.0
+    F[:, 1] = pos @ [-0.6, 0.8, 0.3] - 0.2
+    o, d = _axis_ray(h, lo, 0.4, 0.2)
+    hits = trace_hits(oc, o, d, 4)
+    rgb, dep, acc, st = render_lf(oc, F, p, dec, o, d, hits, tau_mode="direct")
+    x1 = o[0].astype(np.float64) + 2.0 * d[0]
+    x2 = o[0].astype(np.float64) + (2.0 + h) * d[0]
+    sigma = max(x1 @ [1.5, 0.2, -0.4] + 1.0, 0.0)
+    eta = 1.0 / (1.0 + np.exp(-(x2 @ [-0.6, 0.8, 0.3] - 0.2)))
+    assert sigma > 0
+    alpha = 1.0 - np.exp(-sigma)
+    np.testing.assert_allclose(acc[0], alpha, rtol=1e-12)
+    np.testing.assert_allclose(dep[0], alpha * (eta * 2.0 + (1 - eta) * (2.0 + h)), rtol=1e-12)
+    # colour decoder with zero weights: c = 1/2
+    np.testing.assert_allclose(rgb[0], 0.5 * alpha, rtol=1e-12)
+
+
+def test_ray_parameterisation_reaches_the_colour_decoder():
+    """Colour channel 0 = sigmoid(r_0) (x of p1~), channel 1 = sigmoid(r_3)
+    (x of p2~), channel 2 = sigmoid(d_x) with the view direction: for a +x
+    ray through the voxel centre r_0 = -1, r_3 = +1."""
+    oc, h, lo = _one_voxel()
+    dec = (1, 1, 4, 1, 1)
+    wt, wc = widths_of(dec, viewdir=True)
+    lt, lc = _zeros(wt), _zeros(wc)
+    lt[-1][1][:] = [2.0, 0.0]
+    W0, b0 = lc[0]
+    W0[0, 1 + 0] = 1.0                             # input = [z_C (1) | r (6) | d (3)]
+    W0[1, 1 + 3] = 1.0
+    W0[2, 1 + 6] = 1.0
+    b0[:3] = 10.0
+    W1, b1 = lc[1]
+    W1[0, 0] = W1[1, 1] = W1[2, 2] = 1.0
+    b1[:] = -10.0
+    p = np.concatenate([_layers_flat(lt), _layers_flat(lc)])
+    F = np.zeros((oc.n_vertices, 2))
+    o, d = _axis_ray(h, lo, 0.5, 0.5)
+    hits = trace_hits(oc, o, d, 4)
+    rgb, _, acc, st = render_lf(oc, F, p, dec, o, d, hits, viewdir=True)
+    np.testing.assert_allclose(st.r[0], [-1, 0, 0, 1, 0, 0], atol=1e-12)
+    sg = lambda x: 1.0 / (1.0 + np.exp(-x))
+    np.testing.assert_allclose(rgb[0], acc[0] * sg(np.array([-1.0, 1.0, 1.0])), rtol=1e-12)
+
+
+# ------------------------------------------------------------ gradients
+
+def _fd_case(seed, tau_mode, viewdir=False):
+    w = tiny_workload(seed, 3, 7, (8, 16, 16, 4), 4, n_obj=2)
+    sc = w.scene()
+    oc = Octree(sc.leaf_ijk, sc.depth)
+    dec = (4, 3, 16, 1, 2)
+    rng = np.random.default_rng(seed)
+    F = rng.normal(0, 1.0, (oc.n_vertices, 7))
+    wt, wc = widths_of(dec, viewdir)
+    p = np.concatenate([xavier_params(rng, wt), xavier_params(rng, wc)]).astype(np.float64)
+    nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
+    p[nt - 2] = 0.8                                # sigma mostly positive
+    o, d = random_rays(rng, 48, inside_frac=0.1, axis_frac=0.0)
+    hits = trace_hits(oc, o, d, 4)
+    rgb_t = rng.uniform(0, 1, (48, 3))
+    dep_t = rng.uniform(0, 4, 48)
+    return oc, F, p, dec, o, d, hits, rgb_t, dep_t
+
+
+def _pattern(st, dep, dep_t):
+    return np.concatenate([np.concatenate([z.ravel() > 0 for z in st.presT + st.presC]),
+                           st.oT[:, 0] > 0, dep - dep_t > 0,
+                           ((st.us_raw >= 0) & (st.us_raw <= 1)).ravel()])
+
+
+@pytest.mark.parametrize("tau_mode,viewdir", [("direct", False), ("voxel", False), ("direct", True)])
+def test_lf_gradients_against_central_differences(tau_mode, viewdir):
+    oc, F, p, dec, o, d, hits, rgb_t, dep_t = _fd_case(5, tau_mode, viewdir)
+
+    def L(Fx, px):
+        rgb, dep, acc, st = render_lf(oc, Fx, px, dec, o, d, hits, tau_mode=tau_mode, viewdir=viewdir)
+        return loss(rgb, dep, rgb_t, dep_t)[0], st, rgb, dep
+
+    L0, st, rgb, dep = L(F, p)
+    assert st.ray_i.size > 20
+    base = _pattern(st, dep, dep_t)
+    _, g_rgb, g_dep = loss(rgb, dep, rgb_t, dep_t)
+    gF, gp = render_lf_backward(st, g_rgb, g_dep)
+    assert np.abs(gF[:, :4]).max() > 0 and np.abs(gF[:, 4:]).max() > 0
+
+    def fd(Fp, Fm, pp, pm, eps):
+        Lp, sp, _, dp = L(Fp, pp)
+        Lm, sm, _, dm = L(Fm, pm)
+        if not (np.array_equal(_pattern(sp, dp, dep_t), base) and np.array_equal(_pattern(sm, dm, dep_t), base)):
+            return None
+        return (Lp - Lm) / (2 * eps)
+
+    floor = lambda eps: 64 * np.finfo(np.float64).eps * abs(L0) / eps
+    rng = np.random.default_rng(1)
+    touched = np.unique(st.corners)
+    checked = skipped = 0
+    for _ in range(60):
+        v = touched[rng.integers(touched.size)]
+        c = rng.integers(0, F.shape[1])
+        eps = 1e-6
+        Fp = F.copy(); Fp[v, c] += eps
+        Fm = F.copy(); Fm[v, c] -= eps
+        g = fd(Fp, Fm, p, p, eps)
+        if g is None:
+            skipped += 1
+            continue
+        checked += 1
+        assert abs(g - gF[v, c]) <= 1e-6 * abs(g) + floor(eps), (v, c, g, gF[v, c])
+    for k in rng.choice(p.size, 80, replace=False):
+        eps = 1e-6
+        pp = p.copy(); pp[k] += eps
+        pm = p.copy(); pm[k] -= eps
+        g = fd(F, F, pp, pm, eps)
+        if g is None:
+            skipped += 1
+            continue
+        checked += 1
+        assert abs(g - gp[k]) <= 1e-6 * abs(g) + floor(eps), (k, g, gp[k])
+    assert skipped <= 0.1 * (checked + skipped)
+
+
+def test_eta_gradient_through_the_surface_point():
+    """With a constant eta path only (colour features a linear field, colour
+    decoder the identity), dL/dbeta (the eta output bias) equals the closed
+    form sum over channels of dL/dc * c(1-c) * A (x1 - x2) * eta(1-eta)
+    plus the depth term."""
+    oc, h, lo = _one_voxel()
+    dec = (2, 3, 4, 1, 1)
+    wt, wc = widths_of(dec)
+    lt, lc = _zeros(wt), _zeros(wc)
+    beta, s = 0.4, 0.9
+    lt[-1][1][:] = [s, beta]
+    W0, b0 = lc[0]
+    W0[0, 0] = W0[1, 1] = W0[2, 2] = 1.0
+    b0[:3] = 10.0
+    W1, b1 = lc[1]
+    W1[0, 0] = W1[1, 1] = W1[2, 2] = 1.0
+    b1[:] = -10.0
+    p = np.concatenate([_layers_flat(lt), _layers_flat(lc)])
+    A = np.array([[0.8, -0.3, 0.5], [-0.2, 0.9, 0.1], [0.4, 0.4, -0.7]])
+    F = np.zeros((oc.n_vertices, 5))
+    F[:, 2:] = _vertex_pos(oc, h) @ A.T + 0.1
+    o, d = _axis_ray(h, lo)
+    hits = trace_hits(oc, o, d, 4)
+    rgb, dep, acc, st = render_lf(oc, F, p, dec, o, d, hits)
+    g_rgb = np.array([[0.3, -0.7, 0.2]])
+    g_dep = np.array([0.5])
+    _, gp = render_lf_backward(st, g_rgb, g_dep)
+    nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
+    eta = 1.0 / (1.0 + np.exp(-beta))
+    alpha = 1.0 - np.exp(-s)
+    x1 = o[0].astype(np.float64) + 2.0 * d[0]
+    x2 = o[0].astype(np.float64) + (2.0 + h) * d[0]
+    xs = eta * x1 + (1 - eta) * x2
+    c = 1.0 / (1.0 + np.exp(-(A @ xs + 0.1)))
+    dL_deta = alpha * (g_rgb[0] * c * (1 - c)) @ (A @ (x1 - x2)) + alpha * g_dep[0] * (2.0 - (2.0 + h))
+    np.testing.assert_allclose(gp[nt - 1], dL_deta * eta * (1 - eta), rtol=1e-12)
+
+
+def test_feature_gradient_conservation():
+    oc, F, p, dec, o, d, hits, _, _ = _fd_case(9, "direct")
+    rgb, dep, acc, st = render_lf(oc, F, p, dec, o, d, hits)
+    rng = np.random.default_rng(2)
+    g_rgb = rng.normal(size=rgb.shape)
+    g_dep = rng.normal(size=dep.shape)
+    gF, _ = render_lf_backward(st, g_rgb, g_dep)
+    # trilinear weights sum to one: a perturbation of all of Z_C by a constant vector e shifts psi(x_s) by
+    # e exactly: the directional derivative equals sum(gF_C) . e
+    e = rng.normal(size=3)
+    eps = 1e-6
+    Fp = F.copy(); Fp[:, 4:] += eps * e
+    Fm = F.copy(); Fm[:, 4:] -= eps * e
+    r1 = render_lf(oc, Fp, p, dec, o, d, hits)
+    r2 = render_lf(oc, Fm, p, dec, o, d, hits)
+    fd = (np.sum(g_rgb * (r1[0] - r2[0])) + np.sum(g_dep * (r1[1] - r2[1]))) / (2 * eps)
+    assert abs(fd - gF[:, 4:].sum(axis=0) @ e) <= 1e-6 * abs(fd) + 1e-8
+    # the same for Z_T (both points share the voxel's corners)
+    e = rng.normal(size=4)
+    Fp = F.copy(); Fp[:, :4] += eps * e
+    Fm = F.copy(); Fm[:, :4] -= eps * e
+    r1 = render_lf(oc, Fp, p, dec, o, d, hits)
+    r2 = render_lf(oc, Fm, p, dec, o, d, hits)
+    fd = (np.sum(g_rgb * (r1[0] - r2[0])) + np.sum(g_dep * (r1[1] - r2[1]))) / (2 * eps)
+    assert abs(fd - gF[:, :4].sum(axis=0) @ e) <= 1e-6 * abs(fd) + 1e-8
