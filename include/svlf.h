@@ -18,6 +18,9 @@
  *   svlf_adam_step      Adam update of an FP32 parameter vector (section 4.5
  *                       trains with Adam)
  *   svlf_lazy_adam_step Adam restricted to the feature rows a batch touched
+ *   svlf_lf_*           the same path with the paper's two-decoder light-field
+ *                       function (ray parameterisation, tau and eta from the
+ *                       entry / exit features, colour at the surface point)
  *
  * Conventions shared by every call
  * --------------------------------
@@ -258,6 +261,79 @@ int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* r
                     float* out_rgb, float* out_depth, float* loss_out,
                     float* const* grad_features, float* grad_params,
                     void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- light field */
+
+/* The paper's voxel light-field function (section 4.2, Eq. 1-2) in place of
+ * the single decoder: for every crossed voxel (entry point x1 = o + t_in d,
+ * exit point x2 = o + t_out d),
+ *   r      = the two points where the ray meets the voxel's bounding sphere
+ *            (centre lo + h/2, radius h sqrt(3)/2), as unit vectors from the
+ *            centre, in order along the ray (6 values; section 4.1);
+ *   (tau, eta) from the density decoder F_T on [psi(x1; Z_T) | psi(x2; Z_T) | r]
+ *            (2 C_T + 6 inputs): tau = ReLU(o_0) (scaled by dt/h or dt in the
+ *            VOXEL / WORLD tau modes; DIRECT is the paper's form), eta =
+ *            sigmoid(o_1);
+ *   x_s    = eta x1 + (1 - eta) x2, t_s = eta t_in + (1 - eta) t_out;
+ *   c      = sigmoid of the colour decoder F_C on [psi(x_s; Z_C) | r]
+ *            (C_C + 6 inputs, + 3 for the ray direction d with
+ *            SVLF_FLAG_VIEWDIR);
+ * composited with Eq. 3 (depth = sum w_i t_s,i).  psi is the trilinear
+ * interpolation of the voxel's corner embeddings with u clamped to [0,1].
+ * Features: one table per scene, [n_vertices][C_T + C_C] FP32 (Z_T columns
+ * first; features_bf16 the same shape in BF16 for the BF16 precision).
+ * params: FP32, F_T's layers then F_C's, each W[out][in] then b[out]
+ * (svlf_lf_param_count()).  Supported: C_T = 64, C_C = 32, hidden width
+ * 128, one hidden layer in F_T and three in F_C (the paper's sizes, section
+ * 4.5).  Hidden layers ReLU; BF16 rounds features, weights, both decoders'
+ * inputs and hidden activations (and each layer's dL/dz in the backward). */
+typedef struct {
+  int32_t c_density;          /* C_T: 64                                     */
+  int32_t c_color;            /* C_C: 32                                     */
+  int32_t hidden;             /* 128                                         */
+  int32_t n_hidden_density;   /* 1                                           */
+  int32_t n_hidden_color;     /* 3                                           */
+  const float* params;        /* device FP32 [svlf_lf_param_count()]         */
+} svlf_lf_model;
+
+/* Number of parameters of the model (with opts->flags' SVLF_FLAG_VIEWDIR),
+ * or 0 with the error set if the model is unsupported. */
+int64_t svlf_lf_param_count(const svlf_lf_model* model, const svlf_render_opts* opts);
+
+/* Workspace bytes for n_rays rays (0 on invalid arguments). */
+size_t svlf_lf_workspace_bytes(const svlf_lf_model* model, const svlf_render_opts* opts,
+                               int64_t n_rays);
+
+/* Forward render with the light-field function; arguments as svlf_render. */
+int svlf_lf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                   const svlf_lf_model* model, const svlf_render_opts* opts,
+                   const float* ray_o, const float* ray_d,
+                   float* out_rgb, float* out_depth, float* out_acc,
+                   void* workspace, size_t ws_bytes, void* stream);
+
+/* Backward of svlf_lf_render (re-traces and recomputes); gradients are
+ * ADDED to grad_features[s] ([n_vertices][C_T + C_C] FP32, FP32 atomics)
+ * and grad_params (FP32 [svlf_lf_param_count()]); arguments otherwise as
+ * svlf_render_backward.  The gradient reaches eta through t_s and through
+ * the interpolation at x_s (the clamp of the cell coordinates passes it
+ * where the unclamped coordinate is in [0, 1]). */
+int svlf_lf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
+                            const int64_t* ray_offsets_host, const svlf_lf_model* model,
+                            const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                            const float* grad_rgb, const float* grad_depth, const float* grad_acc,
+                            float* const* grad_features, float* grad_params,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/* Render + the loss of svlf_train_step + backward, with the light-field
+ * function; arguments as svlf_train_step. */
+int svlf_lf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                       const svlf_lf_model* model, const svlf_render_opts* opts,
+                       const float* ray_o, const float* ray_d,
+                       const float* target_rgb, const float* target_depth,
+                       float lambda_depth, float loss_scale,
+                       float* out_rgb, float* out_depth, float* loss_out,
+                       float* const* grad_features, float* grad_params,
+                       void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- training utilities */
 

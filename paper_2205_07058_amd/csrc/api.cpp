@@ -229,9 +229,190 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   return SVLF_OK;
 }
 
+// ---------------------------------------------------------------- light field
+
+int check_lf_shape(const svlf_lf_model* m, const svlf_render_opts* opts, int64_t* np,
+                   const char* who) {
+  if (m == nullptr) return fail(SVLF_E_INVAL, who_str(who, "model is NULL"));
+  if (m->c_density != kLfCT || m->c_color != kLfCC || m->hidden != kLfH ||
+      m->n_hidden_density != kLfNHT || m->n_hidden_color != kLfNHC)
+    return fail(SVLF_E_UNSUPPORTED,
+                who_str(who, "supported light-field model: C_T 64, C_C 32, hidden 128, 1 + 3 hidden layers"));
+  *np = lf_params_density() + lf_params_color((opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0);
+  return SVLF_OK;
+}
+
+int check_lf_model(const svlf_lf_model* m, const svlf_render_opts* opts, int64_t* np,
+                   const char* who) {
+  int rc = check_lf_shape(m, opts, np, who);
+  if (rc) return rc;
+  if (m->params == nullptr) return fail(SVLF_E_INVAL, who_str(who, "model->params is NULL"));
+  return SVLF_OK;
+}
+
+// Workspace: [hit slots][counts][per-hit state][dL/d(o_T0, o_T1)][decoder
+// packs][per-block partials of F_T][of F_C][per-block loss]
+struct LfLayout {
+  size_t hits, cnt, st, gT, packs, partT, partC, loss, total;
+};
+
+LfLayout lf_layout(int64_t n, int K, int precision, int viewdir) {
+  LfLayout w;
+  const size_t slots = static_cast<size_t>(n) * K;
+  const size_t grid = static_cast<size_t>(lf_grid_limit());
+  size_t off = 0;
+  w.hits = off;
+  off = align256(off + slots * sizeof(HitRec));
+  w.cnt = off;
+  off = align256(off + static_cast<size_t>(n) * sizeof(int32_t));
+  w.st = off;
+  off = align256(off + slots * sizeof(LfHit));
+  w.gT = off;
+  off = align256(off + slots * 2 * sizeof(float));
+  w.packs = off;
+  off = align256(off + lf_pack_bytes(precision, viewdir));
+  w.partT = off;
+  off = align256(off + grid * lf_params_density() * sizeof(float));
+  w.partC = off;
+  off = align256(off + grid * lf_params_color(viewdir) * sizeof(float));
+  w.loss = off;
+  off = align256(off + grid * sizeof(float));
+  w.total = off;
+  return w;
+}
+
+int run_lf_call(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_t* offs,
+                const svlf_lf_model* model, const svlf_render_opts* opts, const float* ray_o,
+                const float* ray_d, LfArgs a, float* const* grad_features, void* ws,
+                size_t ws_bytes, void* stream, const char* who) {
+  int rc = check_opts(opts, who);
+  if (rc) return rc;
+  int64_t np = 0;
+  rc = check_lf_model(model, opts, &np, who);
+  if (rc) return rc;
+  const bool need_grads = mode != kForward;
+  rc = make_table(scenes, n_scenes, offs, opts->precision == SVLF_BF16, grad_features, need_grads,
+                  &a.tab, who);
+  if (rc) return rc;
+  const int64_t n = offs[n_scenes];
+  if (n > 0 && (ray_o == nullptr || ray_d == nullptr))
+    return fail(SVLF_E_INVAL, who_str(who, "ray_o / ray_d is NULL"));
+  const int vd = (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0;
+  const LfLayout w = lf_layout(n, opts->K, opts->precision, vd);
+  if (ws == nullptr || ws_bytes < w.total)
+    return fail(SVLF_E_WORKSPACE, who_str(who, "workspace missing or smaller than svlf_lf_workspace_bytes()"));
+  if (n == 0) return SVLF_OK;
+  char* base = static_cast<char*>(ws);
+  a.o = ray_o;
+  a.d = ray_d;
+  a.hits = reinterpret_cast<HitRec*>(base + w.hits);
+  a.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
+  a.st = reinterpret_cast<LfHit*>(base + w.st);
+  a.gT = reinterpret_cast<float*>(base + w.gT);
+  a.packs = base + w.packs;
+  a.partT = reinterpret_cast<float*>(base + w.partT);
+  a.partC = reinterpret_cast<float*>(base + w.partC);
+  a.ws_loss = reinterpret_cast<float*>(base + w.loss);
+  a.K = opts->K;
+  a.tau_mode = opts->tau_mode;
+  a.precision = opts->precision;
+  a.viewdir = vd;
+  a.params = model->params;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (!(opts->flags & SVLF_FLAG_REUSE_HITS)) {
+    e = launch_trace_internal(a.tab, ray_o, ray_d, opts->K, const_cast<HitRec*>(a.hits),
+                              const_cast<int32_t*>(a.cnt), s);
+    if (e != hipSuccess) return hip_fail(e, who);
+  }
+  if (opts->flags & SVLF_FLAG_TRACE_ONLY) return SVLF_OK;
+  e = launch_lf(a, mode, s);
+  if (e != hipSuccess) return hip_fail(e, who);
+  return SVLF_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int64_t svlf_lf_param_count(const svlf_lf_model* model, const svlf_render_opts* opts) {
+  const char* who = "svlf_lf_param_count";
+  if (check_opts(opts, who)) return 0;
+  int64_t np = 0;
+  if (check_lf_shape(model, opts, &np, who)) return 0;
+  return np;
+}
+
+size_t svlf_lf_workspace_bytes(const svlf_lf_model* model, const svlf_render_opts* opts,
+                               int64_t n_rays) {
+  const char* who = "svlf_lf_workspace_bytes";
+  if (check_opts(opts, who)) return 0;
+  if (svlf_lf_param_count(model, opts) == 0) return 0;
+  if (n_rays < 0) {
+    fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
+    return 0;
+  }
+  return lf_layout(n_rays, opts->K, opts->precision, (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0).total;
+}
+
+int svlf_lf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                   const svlf_lf_model* model, const svlf_render_opts* opts, const float* ray_o,
+                   const float* ray_d, float* out_rgb, float* out_depth, float* out_acc,
+                   void* workspace, size_t ws_bytes, void* stream) {
+  const char* who = "svlf_lf_render";
+  if (out_rgb == nullptr || out_depth == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "out_rgb / out_depth is NULL"));
+  LfArgs a{};
+  a.rgb = out_rgb;
+  a.depth = out_depth;
+  a.acc = out_acc;
+  return run_lf_call(kForward, scenes, n_scenes, ray_offsets_host, model, opts, ray_o, ray_d, a,
+                     nullptr, workspace, ws_bytes, stream, who);
+}
+
+int svlf_lf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
+                            const int64_t* ray_offsets_host, const svlf_lf_model* model,
+                            const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                            const float* grad_rgb, const float* grad_depth, const float* grad_acc,
+                            float* const* grad_features, float* grad_params, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  const char* who = "svlf_lf_render_backward";
+  if (grad_rgb == nullptr || grad_depth == nullptr || grad_params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "grad_rgb / grad_depth / grad_params is NULL"));
+  LfArgs a{};
+  a.g_rgb = grad_rgb;
+  a.g_depth = grad_depth;
+  a.g_acc = grad_acc;
+  a.grad_params = grad_params;
+  return run_lf_call(kBackward, scenes, n_scenes, ray_offsets_host, model, opts, ray_o, ray_d, a,
+                     grad_features, workspace, ws_bytes, stream, who);
+}
+
+int svlf_lf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,
+                       const svlf_lf_model* model, const svlf_render_opts* opts,
+                       const float* ray_o, const float* ray_d, const float* target_rgb,
+                       const float* target_depth, float lambda_depth, float loss_scale,
+                       float* out_rgb, float* out_depth, float* loss_out,
+                       float* const* grad_features, float* grad_params, void* workspace,
+                       size_t ws_bytes, void* stream) {
+  const char* who = "svlf_lf_train_step";
+  if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
+  if (!std::isfinite(lambda_depth) || !std::isfinite(loss_scale))
+    return fail(SVLF_E_INVAL, who_str(who, "lambda_depth / loss_scale must be finite"));
+  LfArgs a{};
+  a.t_rgb = target_rgb;
+  a.t_depth = target_depth;
+  a.lambda_depth = lambda_depth;
+  a.loss_scale = loss_scale;
+  a.rgb = out_rgb;
+  a.depth = out_depth;
+  a.loss_out = loss_out;
+  a.grad_params = grad_params;
+  return run_lf_call(kTrain, scenes, n_scenes, ray_offsets_host, model, opts, ray_o, ray_d, a,
+                     grad_features, workspace, ws_bytes, stream, who);
+}
+
 
 const char* svlf_last_error(void) { return svlf::error_cstr(); }
 

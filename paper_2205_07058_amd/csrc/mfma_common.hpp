@@ -1,0 +1,125 @@
+// Building blocks shared by the shading kernels: gfx950 MFMA wrappers and
+// their operand layouts, bfloat16 rounding, block-wide scan and sum.
+//
+// MFMA layouts (32x32 result tiles, 64 lanes, lane group g = lane / 32):
+//  * v_mfma_f32_32x32x16_bf16: A lane l holds row l % 32, K = 8 g + j
+//    (j = 0..7); B lane l holds column l % 32, the same K; result register i
+//    of lane l is row drow(i, g), column l % 32;
+//  * v_mfma_f32_32x32x2f32: A / B lane l holds row / column l % 32, K = g;
+//    the result layout is the same.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+namespace svlf {
+namespace detail {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// FP32 -> bfloat16 bits, round to nearest even.
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return static_cast<short>((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+__device__ __forceinline__ f32x16 mma(s16x8 a, s16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mma(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x16 zero16() {
+  f32x16 z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = 0.0f;
+  return z;
+}
+
+// Row (output feature within a 32-tile) of register i of a 32x32 MFMA result
+// held by a lane of group g = lane / 32.
+__device__ __forceinline__ constexpr int drow(int i, int g) { return 8 * (i >> 2) + 4 * g + (i & 3); }
+
+// K index of step s, lane group g, element j for an operand that comes from
+// a 32x32 result tile (D layout, see drow).
+template <bool BF>
+__device__ __forceinline__ int kmap_d(int s, int g, int j) {
+  if (BF) return 32 * (s >> 1) + 8 * (2 * (s & 1) + (j >> 2)) + 4 * g + (j & 3);
+  return 32 * (s >> 4) + 8 * ((s & 15) >> 2) + 4 * g + (s & 3);
+}
+// K index of an operand read row-wise from an LDS tile [hit][k].
+template <bool BF>
+__device__ __forceinline__ int kmap_x(int s, int g, int j) {
+  if (BF) return 16 * s + 8 * g + j;
+  return 4 * (2 * (s >> 2) + g) + (s & 3);
+}
+
+constexpr int align16(int x) { return (x + 15) & ~15; }
+constexpr int align8(int x) { return (x + 7) & ~7; }
+constexpr int align32(int x) { return (x + 31) & ~31; }
+
+__device__ __forceinline__ void relu16(f32x16& t) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = t[i] > 0.0f ? t[i] : 0.0f;
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// Exclusive prefix sum of v over the block's NW waves (scr: NW ints of LDS).
+template <int NW>
+__device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) scr[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int t = scr[i];
+    pre += (i < w) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+template <int NW>
+__device__ __forceinline__ float block_sum(float v, float* scr) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) scr[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float t = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += scr[i];
+  __syncthreads();
+  return t;
+}
+
+}  // namespace detail
+}  // namespace svlf

@@ -90,6 +90,61 @@ struct ShadeArgs {
 
 enum ShadeMode { kForward = 0, kBackward = 1, kTrain = 2 };
 
+// ---------------------------------------------------------------- light field
+// The paper's two-decoder function (svlf_lf_*): per-hit state written by the
+// density kernel and read by the colour kernel.
+struct LfHit {
+  float us[3];            // surface point in cell units (unclamped)
+  float ts;               // its ray parameter
+  float alpha;            // 1 - e^-tau
+  float e;                // e^-tau
+  float dtau;             // d tau / d o_T0 (0 where the ReLU is off)
+  float eta;
+};
+
+// Supported light-field decoders: C_T = 64, C_C = 32, H = 128, one hidden
+// layer in the density decoder and three in the colour decoder.
+constexpr int kLfCT = 64, kLfCC = 32, kLfH = 128, kLfNHT = 1, kLfNHC = 3;
+int lf_grid_limit();      // blocks of each light-field kernel (workspace partials)
+int64_t lf_params_density();
+int64_t lf_params_color(int viewdir);
+size_t lf_pack_bytes(int precision, int viewdir);   // both decoders' MFMA packs
+
+struct LfArgs {
+  SceneTable tab;
+  const float* o;
+  const float* d;
+  const HitRec* hits;
+  const int32_t* cnt;
+  int32_t K;
+  int32_t tau_mode;
+  int32_t precision;
+  int32_t viewdir;
+  const float* params;    // FP32 masters: density layers then colour layers
+  LfHit* st;              // [n][K]
+  float* gT;              // [n][K][2]: dL/d(o_T0, o_T1)
+  void* packs;            // lf_pack_bytes()
+  float* rgb;
+  float* depth;
+  float* acc;
+  const float* g_rgb;
+  const float* g_depth;
+  const float* g_acc;
+  const float* t_rgb;
+  const float* t_depth;
+  float lambda_depth;
+  float loss_scale;
+  float* loss_out;
+  float* grad_params;
+  float* partT;           // [grid][params_density]
+  float* partC;           // [grid][params_color]
+  float* ws_loss;         // [grid]
+};
+
+// Runs packing, the density kernel, the colour kernel and (backward / train)
+// the density backward and the reductions of the decoder gradients.
+hipError_t launch_lf(const LfArgs& a, int mode, hipStream_t s);
+
 hipError_t launch_shade(const ShadeArgs& a, int mode, hipStream_t s, int* grid_used);
 size_t shade_workspace_bytes(int64_t n_params, int n_rays_hint);
 int shade_grid_limit();

@@ -60,6 +60,16 @@ class RenderOpts(ct.Structure):
                 ("flags", ct.c_int32)]
 
 
+class LfModel(ct.Structure):
+    _fields_ = [("c_density", ct.c_int32), ("c_color", ct.c_int32), ("hidden", ct.c_int32),
+                ("n_hidden_density", ct.c_int32), ("n_hidden_color", ct.c_int32),
+                ("params", ct.c_void_p)]
+
+
+# The light-field decoders the library supports (the paper's sizes):
+# (C_T, C_C, hidden, hidden layers of F_T, hidden layers of F_C)
+LF_DECODERS = (64, 32, 128, 1, 3)
+
 _lib = None
 
 _SIGS = {
@@ -91,6 +101,20 @@ _SIGS = {
     "svlf_lazy_adam_step": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
                              ct.c_int32, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_int64,
                              ct.c_void_p, ct.c_int32, ct.c_void_p], ct.c_int),
+    "svlf_lf_param_count": ([ct.POINTER(LfModel), ct.POINTER(RenderOpts)], ct.c_int64),
+    "svlf_lf_workspace_bytes": ([ct.POINTER(LfModel), ct.POINTER(RenderOpts), ct.c_int64], ct.c_size_t),
+    "svlf_lf_render": ([ct.POINTER(Scene), ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(LfModel),
+                        ct.POINTER(RenderOpts), ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                        ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p], ct.c_int),
+    "svlf_lf_render_backward": ([ct.POINTER(Scene), ct.c_int32, ct.POINTER(ct.c_int64),
+                                 ct.POINTER(LfModel), ct.POINTER(RenderOpts), ct.c_void_p,
+                                 ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                 ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p], ct.c_int),
+    "svlf_lf_train_step": ([ct.POINTER(Scene), ct.c_int32, ct.POINTER(ct.c_int64),
+                            ct.POINTER(LfModel), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_void_p,
+                            ct.c_void_p, ct.c_void_p, ct.c_float, ct.c_float, ct.c_void_p,
+                            ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                            ct.c_size_t, ct.c_void_p], ct.c_int),
     "svlf_to_bf16": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_fill": ([ct.c_void_p, ct.c_float, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_mlp_forward": ([ct.POINTER(Mlp), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_int64,
@@ -475,3 +499,111 @@ def mlp_forward(params, widths, opts: RenderOpts, X):
                                    _ptr(X, torch.float32, (n, widths[0]), "X"), n, _ptr(out),
                                    _stream()))
     return out
+
+
+# ------------------------------------------------------------------ light field
+
+def make_lf_model(params=None) -> LfModel:
+    m = LfModel()
+    m.c_density, m.c_color, m.hidden, m.n_hidden_density, m.n_hidden_color = LF_DECODERS
+    m.params = params.data_ptr() if params is not None else None
+    return m
+
+
+def lf_param_count(opts: RenderOpts) -> int:
+    m = make_lf_model()
+    n = load().svlf_lf_param_count(ct.byref(m), ct.byref(opts))
+    if n == 0:
+        raise SvlfError("svlf_lf_param_count", E_INVAL, last_error())
+    return int(n)
+
+
+def lf_workspace_bytes(opts: RenderOpts, n_rays) -> int:
+    m = make_lf_model()
+    nb = load().svlf_lf_workspace_bytes(ct.byref(m), ct.byref(opts), int(n_rays))
+    if nb == 0:
+        raise SvlfError("svlf_lf_workspace_bytes", E_INVAL, last_error())
+    return nb
+
+
+def _lf_params(params, opts):
+    torch = _torch()
+    return _ptr(params, torch.float32, (lf_param_count(opts),), "params").value
+
+
+def lf_render(scenes, ray_counts, params, opts: RenderOpts, ray_o, ray_d, out_rgb=None,
+              out_depth=None, out_acc=None, workspace: Workspace = None):
+    """Render with the paper's two-decoder light-field function; features of
+    each scene are [n_vertices][C_T + C_C]."""
+    torch = _torch()
+    scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
+    arr, offs, n = _scene_array(scenes, ray_counts)
+    dev = ray_o.device
+    out_rgb = torch.empty((n, 3), dtype=torch.float32, device=dev) if out_rgb is None else out_rgb
+    out_depth = torch.empty((n,), dtype=torch.float32, device=dev) if out_depth is None else out_depth
+    if out_acc is None:
+        out_acc = torch.empty((n,), dtype=torch.float32, device=dev)
+    m = make_lf_model()
+    m.params = _lf_params(params, opts)
+    nb = lf_workspace_bytes(opts, n)
+    ws = (workspace or _default_ws).get(nb, dev)
+    _check("svlf_lf_render",
+           load().svlf_lf_render(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),
+                                 _ptr(ray_o, torch.float32, (n, 3), "ray_o"),
+                                 _ptr(ray_d, torch.float32, (n, 3), "ray_d"),
+                                 _ptr(out_rgb, torch.float32, (n, 3), "out_rgb"),
+                                 _ptr(out_depth, torch.float32, (n,), "out_depth"),
+                                 _ptr(out_acc, torch.float32, (n,), "out_acc"),
+                                 _ptr(ws, torch.uint8), nb, _stream()))
+    return out_rgb, out_depth, out_acc
+
+
+def lf_render_backward(scenes, ray_counts, params, opts: RenderOpts, ray_o, ray_d, grad_rgb,
+                       grad_depth, grad_acc, grad_features, grad_params,
+                       workspace: Workspace = None):
+    torch = _torch()
+    scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
+    arr, offs, n = _scene_array(scenes, ray_counts)
+    m = make_lf_model()
+    m.params = _lf_params(params, opts)
+    nb = lf_workspace_bytes(opts, n)
+    ws = (workspace or _default_ws).get(nb, ray_o.device)
+    for g, s in zip(grad_features, scenes):
+        _ptr(g, torch.float32, tuple(s.features.shape), "grad_features")
+    _check("svlf_lf_render_backward",
+           load().svlf_lf_render_backward(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),
+                                          _ptr(ray_o, torch.float32, (n, 3), "ray_o"),
+                                          _ptr(ray_d, torch.float32, (n, 3), "ray_d"),
+                                          _ptr(grad_rgb, torch.float32, (n, 3), "grad_rgb"),
+                                          _ptr(grad_depth, torch.float32, (n,), "grad_depth"),
+                                          _ptr(grad_acc, torch.float32, (n,), "grad_acc", allow_none=True),
+                                          _grad_ptrs(grad_features),
+                                          _ptr(grad_params, torch.float32, tuple(params.shape), "grad_params"),
+                                          _ptr(ws, torch.uint8), nb, _stream()))
+
+
+def lf_train_step(scenes, ray_counts, params, opts: RenderOpts, ray_o, ray_d, target_rgb,
+                  target_depth, lambda_depth, loss_scale, grad_features, grad_params,
+                  out_rgb=None, out_depth=None, loss_out=None, workspace: Workspace = None):
+    torch = _torch()
+    scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
+    arr, offs, n = _scene_array(scenes, ray_counts)
+    m = make_lf_model()
+    m.params = _lf_params(params, opts)
+    nb = lf_workspace_bytes(opts, n)
+    ws = (workspace or _default_ws).get(nb, ray_o.device)
+    for g, s in zip(grad_features, scenes):
+        _ptr(g, torch.float32, tuple(s.features.shape), "grad_features")
+    _check("svlf_lf_train_step",
+           load().svlf_lf_train_step(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),
+                                     _ptr(ray_o, torch.float32, (n, 3), "ray_o"),
+                                     _ptr(ray_d, torch.float32, (n, 3), "ray_d"),
+                                     _ptr(target_rgb, torch.float32, (n, 3), "target_rgb"),
+                                     _ptr(target_depth, torch.float32, (n,), "target_depth"),
+                                     float(lambda_depth), float(loss_scale),
+                                     _ptr(out_rgb, torch.float32, (n, 3), "out_rgb", allow_none=True),
+                                     _ptr(out_depth, torch.float32, (n,), "out_depth", allow_none=True),
+                                     _ptr(loss_out, torch.float32, (1,), "loss_out", allow_none=True),
+                                     _grad_ptrs(grad_features),
+                                     _ptr(grad_params, torch.float32, tuple(params.shape), "grad_params"),
+                                     _ptr(ws, torch.uint8), nb, _stream()))

@@ -135,3 +135,88 @@ class Case:
         hits = oracle_trace(self.oc, o, d, self.K)
         return oracle_render(self.oc, self.F, self.p, self.widths, o, d, hits,
                              tau_mode=self.tau_mode, bf16=bf16, viewdir=self.viewdir)
+
+
+class LfCase:
+    """A scene with the two-decoder light-field model on the device and in
+    the oracle (features [n_vertices][C_T + C_C])."""
+
+    def __init__(self, svlf, leaf_ijk, depth, features, params, K, tau_mode="direct", viewdir=False):
+        import torch
+        from oracle.lightfield import n_params
+        self.svlf = svlf
+        self.K = K
+        self.tau_mode = tau_mode
+        self.viewdir = viewdir
+        self.dec = tuple(svlf.LF_DECODERS)
+        self.F = np.ascontiguousarray(features, np.float32)
+        self.p = np.ascontiguousarray(params, np.float32)
+        assert self.p.size == n_params(self.dec, viewdir)
+        self.oc = Octree(leaf_ijk, depth)
+        self.scene = svlf.DeviceScene.from_host(leaf_ijk, depth, self.F, bf16=True)
+        self.params = torch.from_numpy(self.p).cuda()
+
+    @classmethod
+    def random(cls, svlf, seed, depth, n_obj=3, feat_sd=0.5, sigma_bias=0.5, K=8, tau_mode="direct",
+               viewdir=False, rule="surface"):
+        from synth.configs import tiny_workload, xavier_params
+        from oracle.lightfield import widths_of
+        w = tiny_workload(seed, depth, 8, (8, 32, 32, 4), K, n_obj=n_obj, rule=rule)
+        sc = w.scene()
+        rng = np.random.default_rng(seed + 1000)
+        dec = tuple(svlf.LF_DECODERS)
+        F = rng.normal(0, feat_sd, (sc.n_vertices, dec[0] + dec[1])).astype(np.float32)
+        wt, wc = widths_of(dec, viewdir)
+        pt = xavier_params(rng, wt)
+        pt[-2] = sigma_bias                      # bias of o_T0 (tau)
+        p = np.concatenate([pt, xavier_params(rng, wc)])
+        return cls(svlf, sc.leaf_ijk, sc.depth, F, p, K, tau_mode, viewdir)
+
+    def opts(self, precision="fp32"):
+        return self.svlf.make_opts(self.K, self.tau_mode, precision,
+                                   self.svlf.FLAG_VIEWDIR if self.viewdir else 0)
+
+    def rays(self, o, d):
+        import torch
+        return (torch.from_numpy(np.ascontiguousarray(o, np.float32)).cuda(),
+                torch.from_numpy(np.ascontiguousarray(d, np.float32)).cuda())
+
+    def oracle(self, o, d, bf16=False):
+        from oracle.lightfield import render_lf
+        hits = oracle_trace(self.oc, o, d, self.K)
+        return render_lf(self.oc, self.F, self.p, self.dec, o, d, hits, tau_mode=self.tau_mode,
+                         bf16=bf16, viewdir=self.viewdir)
+
+    def gpu_render(self, o, d, precision="fp32"):
+        import torch
+        to, td = self.rays(o, d)
+        rgb, dep, acc = self.svlf.lf_render([self.scene], [o.shape[0]], self.params,
+                                            self.opts(precision), to, td)
+        torch.cuda.synchronize()
+        return rgb.cpu().numpy(), dep.cpu().numpy(), acc.cpu().numpy()
+
+    def gpu_backward(self, o, d, g_rgb, g_dep, g_acc=None, precision="fp32"):
+        import torch
+        to, td = self.rays(o, d)
+        gF = torch.zeros(self.scene.features.shape, dtype=torch.float32, device="cuda")
+        gp = torch.zeros(self.params.shape, dtype=torch.float32, device="cuda")
+        t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+        self.svlf.lf_render_backward([self.scene], [o.shape[0]], self.params, self.opts(precision),
+                                     to, td, t(g_rgb), t(g_dep), None if g_acc is None else t(g_acc),
+                                     [gF], gp)
+        torch.cuda.synchronize()
+        return gF.cpu().numpy(), gp.cpu().numpy()
+
+    def smooth_rays(self, o, d, margin=1e-4):
+        """Rays none of whose hits is within `margin` of a kink: a ReLU input
+        of either decoder, the tau ReLU, or the clamp of the surface point's
+        cell coordinates."""
+        _, _, _, st = self.oracle(o, d)
+        near = np.zeros(st.oT.shape[0], bool)
+        for z in st.presT + st.presC:
+            near |= np.any(np.abs(z) < margin, axis=1)
+        near |= np.abs(st.oT[:, 0]) < margin
+        near |= np.any((np.abs(st.us_raw) < margin) | (np.abs(st.us_raw - 1.0) < margin), axis=1)
+        keep = np.ones(o.shape[0], bool)
+        keep[np.unique(st.ray_i[near])] = False
+        return np.nonzero(keep)[0]

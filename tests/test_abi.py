@@ -204,3 +204,33 @@ def test_host_octree_matches_oracle(case):
     np.testing.assert_array_equal(nodes.astype(np.int64), exp_nodes)
     np.testing.assert_array_equal(corners, oc.leaf_corners)
     np.testing.assert_array_equal(srt, oc.leaf_ijk)
+
+
+def test_lf_validation(lib):
+    """Light-field entry points reject unsupported models, NULL parameters and
+    short workspaces on the host before any device work."""
+    opts = svlf.make_opts(8)
+    m = svlf.make_lf_model()
+    assert lib.svlf_lf_param_count(ct.byref(m), ct.byref(opts)) > 0
+    n_plain = lib.svlf_lf_param_count(ct.byref(m), ct.byref(opts))
+    vopts = svlf.make_opts(8, flags=svlf.FLAG_VIEWDIR)
+    assert lib.svlf_lf_param_count(ct.byref(m), ct.byref(vopts)) == n_plain + 3 * 128
+    from oracle.lightfield import n_params
+    assert n_plain == n_params(svlf.LF_DECODERS)
+    bad = svlf.make_lf_model()
+    bad.hidden = 64
+    assert lib.svlf_lf_param_count(ct.byref(bad), ct.byref(opts)) == 0
+    assert "light-field" in svlf.last_error()
+    sc = (svlf.Scene * 1)()
+    sc[0].octree.depth = 4
+    offs = (ct.c_int64 * 2)(0, 100)
+    call = lambda mm, ws, wsb: lib.svlf_lf_render(sc, 1, offs, ct.byref(mm), ct.byref(opts),
+                                                  ct.c_void_p(0x10), ct.c_void_p(0x10),
+                                                  ct.c_void_p(0x10), ct.c_void_p(0x10), None,
+                                                  ws, wsb, None)
+    assert call(bad, None, 0) == svlf.E_UNSUPPORTED
+    assert call(m, None, 0) == svlf.E_INVAL                     # params NULL
+    m.params = 0x100
+    need = lib.svlf_lf_workspace_bytes(ct.byref(m), ct.byref(opts), 100)
+    assert need > 100 * 8 * (16 + 32 + 8)
+    assert call(m, ct.c_void_p(0x100), need - 1) == svlf.E_WORKSPACE

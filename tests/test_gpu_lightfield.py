@@ -1,0 +1,113 @@
+"""GPU parity of the paper's two-decoder light-field function (svlf_lf_*:
+ray parameterisation, density decoder on the entry / exit features giving
+tau and eta, colour decoder at the surface point, Eq. 3) against the FP64
+oracle, forward and backward, FP32 and BF16."""
+
+import numpy as np
+import pytest
+
+from oracle.lightfield import render_lf_backward
+from oracle.render import loss as oracle_loss
+from tests.gpu_cases import LfCase, assert_grad_close, assert_outputs_close, psnr
+from tests.helpers import random_rays
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases(svlf):
+    yield "d4", LfCase.random(svlf, 81, 4, n_obj=3, K=8)
+    yield "d5solid", LfCase.random(svlf, 82, 5, n_obj=2, K=6, rule="solid", tau_mode="voxel")
+    yield "d5vd", LfCase.random(svlf, 83, 5, n_obj=3, K=8, viewdir=True)
+
+
+def test_lf_render_fp32(gpu_lib):
+    for name, case in _cases(gpu_lib):
+        rng = np.random.default_rng(len(name))
+        o, d = random_rays(rng, 3001, inside_frac=0.2)
+        o[:3] = [[0.1, 0.2, 0.3], [-2, 0.1, 0.1], [np.inf, 0, 0]]
+        d[:3] = [[0, 0, 0], [1, np.nan, 0], [1, 0, 0]]
+        rgb, dep, acc = case.gpu_render(o, d)
+        er, ed, ea, st = case.oracle(o, d)
+        assert st.ray_i.size > 200, name
+        assert_outputs_close(rgb, er, 1.0, f"{name} rgb")
+        assert_outputs_close(acc, ea, 1.0, f"{name} acc")
+        assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), f"{name} depth")
+        assert np.all(rgb[:3] == 0) and np.all(acc[:3] == 0)
+
+
+def test_lf_render_bf16(gpu_lib):
+    for name, case in _cases(gpu_lib):
+        o, d = random_rays(np.random.default_rng(5), 2000)
+        rgb, dep, acc = case.gpu_render(o, d, "bf16")
+        br, bd, ba, _ = case.oracle(o, d, bf16=True)
+        er, _, _, _ = case.oracle(o, d)
+        assert np.abs(rgb - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4, name
+        assert np.abs(acc - ba).max() <= 2 ** -6 + 1e-4, name
+        S = max(1.0, np.abs(bd).max())
+        assert np.abs(dep - bd).max() <= 2 ** -6 * S + 1e-4 * S, name
+        assert psnr(rgb, er) > 35.0, (name, psnr(rgb, er))
+
+
+def test_lf_backward_fp32(gpu_lib):
+    for name, case in _cases(gpu_lib):
+        rng = np.random.default_rng(17)
+        o, d = random_rays(rng, 2500, inside_frac=0.1)
+        keep = case.smooth_rays(o, d)
+        o, d = o[keep], d[keep]
+        n = o.shape[0]
+        g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+        g_dep = rng.normal(size=n).astype(np.float32)
+        g_acc = rng.normal(size=n).astype(np.float32)
+        gF, gp = case.gpu_backward(o, d, g_rgb, g_dep, g_acc)
+        _, _, _, st = case.oracle(o, d)
+        eF, ep = render_lf_backward(st, g_rgb, g_dep, g_acc)
+        ct = case.dec[0]
+        assert np.abs(eF[:, :ct]).max() > 0 and np.abs(eF[:, ct:]).max() > 0, name
+        assert_grad_close(gF[:, :ct], eF[:, :ct], f"{name} grad Z_T")
+        assert_grad_close(gF[:, ct:], eF[:, ct:], f"{name} grad Z_C")
+        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+
+
+def test_lf_train_step_fp32(gpu_lib):
+    import torch
+    for name, case in list(_cases(gpu_lib))[:2]:
+        rng = np.random.default_rng(23)
+        o, d = random_rays(rng, 2000, inside_frac=0.0)
+        keep = case.smooth_rays(o, d)
+        o, d = o[keep], d[keep]
+        n = o.shape[0]
+        t_rgb = rng.uniform(0, 1, (n, 3)).astype(np.float32)
+        t_dep = rng.uniform(0, 5, n).astype(np.float32)
+        to, td = case.rays(o, d)
+        gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+        gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+        loss_t = torch.zeros(1, dtype=torch.float32, device="cuda")
+        out_rgb = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        out_dep = torch.empty((n,), dtype=torch.float32, device="cuda")
+        case.svlf.lf_train_step([case.scene], [n], case.params, case.opts(), to, td,
+                                torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_dep).cuda(),
+                                0.1, 1.0 / n, [gF], gp, out_rgb, out_dep, loss_t)
+        torch.cuda.synchronize()
+        er, ed, _, st = case.oracle(o, d)
+        L, g_rgb, g_dep = oracle_loss(er, ed, t_rgb, t_dep, 0.1)
+        eF, ep = render_lf_backward(st, g_rgb, g_dep)
+        assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L), name
+        assert_outputs_close(out_rgb.cpu().numpy(), er, 1.0, f"{name} train rgb")
+        assert_outputs_close(out_dep.cpu().numpy(), ed, max(1.0, np.abs(ed).max()), f"{name} train depth")
+        assert_grad_close(gF.cpu().numpy(), eF, f"{name} train grad_features")
+        assert_grad_close(gp.cpu().numpy(), ep, f"{name} train grad_params", rel_nw=1e-4, rel_el=None)
+
+
+def test_lf_backward_bf16(gpu_lib):
+    for name, case in _cases(gpu_lib):
+        rng = np.random.default_rng(29)
+        o, d = random_rays(rng, 2000)
+        n = o.shape[0]
+        g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+        g_dep = rng.normal(size=n).astype(np.float32)
+        gF, gp = case.gpu_backward(o, d, g_rgb, g_dep, None, "bf16")
+        _, _, _, st = case.oracle(o, d, bf16=True)
+        eF, ep = render_lf_backward(st, g_rgb, g_dep)
+        cos = lambda a, b: float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        assert cos(gF, eF) > 0.999 and cos(gp, ep) > 0.999, (name, cos(gF, eF), cos(gp, ep))
+        assert np.linalg.norm(gF - eF) <= 0.05 * np.linalg.norm(eF), name
