@@ -49,6 +49,46 @@ def shade_source_prefix():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def bench_lightfield(torch, svlf, timer, args, w, sc, ob_t, db_t, rgb_tt, dep_tt, ov_t, dv_t,
+                     hits_b, hits_v):
+    """The paper's two-decoder light-field function on the same scene and
+    rays: train pass (BF16, FP32) and forward render of one view."""
+    from synth.configs import lf_inputs
+    F, p = lf_inputs(w.seed, sc.n_vertices)
+    scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    params = torch.from_numpy(p).cuda()
+    n_b, n_v = ob_t.shape[0], ov_t.shape[0]
+    gF = torch.zeros_like(scene.features)
+    gp = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    ws = svlf.Workspace()
+    out = {"model": "density 134-128-2, colour 38-128-128-128-3, features 64+32 per vertex, tau direct"}
+    for prec in ("bf16", "fp32"):
+        opts = svlf.make_opts(w.K, "direct", prec)
+        f = lambda: svlf.lf_train_step([scene], [n_b], params, opts, ob_t, db_t, rgb_tt, dep_tt,
+                                       0.1, 1.0 / n_b, [gF], gp, loss_out=loss, workspace=ws)
+        ms, _ = timer.run(f, args.steps, args.warmup)
+        out[f"train_{prec}_ms"] = round(ms / args.steps, 4)
+        out[f"train_{prec}_rays_per_s"] = round(n_b * args.steps / ms * 1e3, 1)
+        log(f"light field train step {prec}: {ms / args.steps:.3f} ms/step, "
+            f"{n_b * args.steps / ms * 1e3 / 1e6:.1f} M rays/s, loss {loss.item():.5f}")
+        opts = svlf.make_opts(w.K, "direct", prec)
+        bufs = (torch.empty((n_v, 3), device="cuda"), torch.empty(n_v, device="cuda"),
+                torch.empty(n_v, device="cuda"))
+        f = lambda: svlf.lf_render([scene], [n_v], params, opts, ov_t, dv_t, *bufs, workspace=ws)
+        ms, _ = timer.run(f, args.steps, args.warmup)
+        out[f"fwd_view_{prec}_ms"] = round(ms / args.steps, 4)
+        out[f"fwd_view_{prec}_rays_per_s"] = round(n_v * args.steps / ms * 1e3, 1)
+        log(f"light field forward view {prec}: {ms / args.steps:.3f} ms/view, "
+            f"{n_v * args.steps / ms * 1e3 / 1e6:.1f} M rays/s")
+    # MACs per hit: density 134*128 + 128*2, colour 38*128 + 2*128*128 + 128*3
+    macs = 134 * 128 + 128 * 2 + 38 * 128 + 2 * 128 * 128 + 128 * 3
+    out["macs_per_hit_forward"] = macs
+    out["decoder_tflops_fwd_view_bf16"] = round(2 * macs * hits_v / (out["fwd_view_bf16_ms"] * 1e-3) / 1e12, 2)
+    del scene, gF
+    return out
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -63,7 +103,7 @@ def parse():
                     help="rays of the batch the oracle trains on for the CPU baseline")
     ap.add_argument("--psnr-rays", type=int, default=16384)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,copy,"
+                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,lf,copy,"
                          "multi (the ragged 8-scene workload; not in 'all')")
     return ap.parse_args()
 
@@ -101,7 +141,7 @@ def main():
     from synth.configs import get_config
 
     sections = set(args.sections.split(",")) if args.sections != "all" else {
-        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr"}
+        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr", "lf"}
     torch.cuda.set_device(0)
     svlf.load()
     t0 = time.time()
@@ -193,6 +233,10 @@ def main():
         res["touched_rows"] = float((gF != 0).any(dim=1).float().mean().item())
         gF.zero_(), gp.zero_()
         log(f"feature rows touched by one batch: {100 * res['touched_rows']:.1f}%")
+
+    if "lf" in sections:
+        res["lightfield"] = bench_lightfield(torch, svlf, timer, args, w, sc, ob_t, db_t, rgb_tt,
+                                             dep_tt, ov_t, dv_t, hits_b, hits_v)
 
     if "copy" in sections:
         # a plain device copy of known size: calibrates the HBM byte counters
@@ -295,6 +339,7 @@ def main():
         "train_bf16_with_lazy_adam_rays_per_s": round(n_b / (res["step_lazy_adam_ms"] * 1e-3), 1)
         if "step_lazy_adam_ms" in res else None,
         "feature_rows_touched_per_batch": round(res["touched_rows"], 4) if "touched_rows" in res else None,
+        "lightfield": res.get("lightfield"),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
         "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
         "device_copy_gbs": round(res["copy_gbs"], 1) if "copy_gbs" in res else None,

@@ -209,7 +209,7 @@ __device__ __forceinline__ void chunk_fence(int s) {
   if ((s + 1) % CH == 0) __builtin_amdgcn_sched_barrier(0);
 }
 template <bool BF>
-constexpr int kChunk = BF ? 2 : 8;
+constexpr int kChunk = BF ? 4 : 16;
 
 // ------------------------------------------------------------ packing
 
@@ -320,8 +320,12 @@ __device__ __forceinline__ void sphere_r(float y0, float y1, float y2, float dx,
 
 // dW tiles of layer l for one window (K = the window's hits, read
 // transposed from LDS: GZ rows = layer outputs, AT rows = layer inputs),
-// added into this block's partial sums (FP32, parameter layout) by the wave
-// that owns the tile.  Only one tile is live in registers at a time.
+// added into this block's partial sums (FP32, parameter layout).  A tile is
+// owned by one wave, so the additions never collide; they are
+// workgroup-scope atomics only so that the wave does not wait for a load
+// of the old values (the block's partials are private to the block and are
+// read by the reduction kernel after this kernel ends).  Only one tile is
+// live in registers at a time.
 template <bool BF, class M, int l, int WIN, int TS>
 __device__ __forceinline__ void dw_window(const typename Types<BF>::El* GZ,
                                           const typename Types<BF>::El* AT, float* __restrict__ part,
@@ -352,7 +356,9 @@ __device__ __forceinline__ void dw_window(const typename Types<BF>::El* GZ,
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int rowo = 32 * mt + drow(i, g);
-      if (rowo < OR && col < IR) part[M::par_w(l) + rowo * IR + col] += acc[i];
+      if (rowo < OR && col < IR)
+        __hip_atomic_fetch_add(part + M::par_w(l) + rowo * IR + col, acc[i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
@@ -1078,6 +1084,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
         __syncthreads();
         if (has_tile) {
           const int c = lane & 31, hs = lane >> 5;
+#pragma unroll 4
           for (int k = 0; k < 32; k += 2) {
             const int hh = n0 + k + hs;
             const bool ok = hh < tw;
@@ -1201,13 +1208,21 @@ int lf_num_cus() {
   return n;
 }
 
+// Persistent launch: as many blocks as fit on the device at once (registers
+// and LDS), at most `cap` (the backward kernels' partial sums are sized for
+// lf_grid_limit() blocks).
 template <class K>
-hipError_t launch_persistent(K kern, int lds, const LfArgs& a, hipStream_t s, int* grid_out) {
+hipError_t launch_persistent(K kern, int lds, const LfArgs& a, hipStream_t s, int* grid_out,
+                             int cap) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  int grid = lf_num_cus();
-  if (grid > lf_grid_limit()) grid = lf_grid_limit();
+  int per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                   kThreads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int grid = lf_num_cus() * per_cu;
+  if (grid > cap) grid = cap;
   if (grid > a.tab.n_blocks) grid = a.tab.n_blocks;
   if (grid < 1) grid = 1;
   *grid_out = grid;
@@ -1224,16 +1239,19 @@ hipError_t run_lf(const LfArgs& a, int mode, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int g1 = 0, g2 = 0, g3 = 0;
-  e = launch_persistent(k_density<P, kForward>, DCfg<P, kForward>::LDS, a, s, &g1);
+  const int fwd_cap = 4096, bwd_cap = lf_grid_limit();
+  e = launch_persistent(k_density<P, kForward>, DCfg<P, kForward>::LDS, a, s, &g1, fwd_cap);
   if (e != hipSuccess) return e;
   if (mode == kForward)
-    return launch_persistent(k_color<P, kForward, VD>, CCfg<P, kForward, VD>::LDS, a, s, &g2);
+    return launch_persistent(k_color<P, kForward, VD>, CCfg<P, kForward, VD>::LDS, a, s, &g2,
+                             fwd_cap);
   if (mode == kTrain)
-    e = launch_persistent(k_color<P, kTrain, VD>, CCfg<P, kTrain, VD>::LDS, a, s, &g2);
+    e = launch_persistent(k_color<P, kTrain, VD>, CCfg<P, kTrain, VD>::LDS, a, s, &g2, bwd_cap);
   else
-    e = launch_persistent(k_color<P, kBackward, VD>, CCfg<P, kBackward, VD>::LDS, a, s, &g2);
+    e = launch_persistent(k_color<P, kBackward, VD>, CCfg<P, kBackward, VD>::LDS, a, s, &g2,
+                          bwd_cap);
   if (e != hipSuccess) return e;
-  e = launch_persistent(k_density<P, kBackward>, DCfg<P, kBackward>::LDS, a, s, &g3);
+  e = launch_persistent(k_density<P, kBackward>, DCfg<P, kBackward>::LDS, a, s, &g3, bwd_cap);
   if (e != hipSuccess) return e;
   e = launch_reduce_partials(a.partT, g3, D::T::NPARAMS, a.grad_params, nullptr, nullptr, s);
   if (e != hipSuccess) return e;

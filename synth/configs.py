@@ -52,6 +52,30 @@ def param_count(widths):
     return sum(o * i + o for i, o in zip(widths[:-1], widths[1:]))
 
 
+# The light-field model's sizes (C_T, C_C, hidden, hidden layers of the
+# density decoder, of the colour decoder) and its decoders' layer widths.
+LF_DECODERS = (64, 32, 128, 1, 3)
+
+
+def lf_widths(viewdir=False):
+    ct, cc, h, nht, nhc = LF_DECODERS
+    return ((2 * ct + 6,) + (h,) * nht + (2,),
+            (cc + 6 + (3 if viewdir else 0),) + (h,) * nhc + (3,))
+
+
+def lf_inputs(seed, n_vertices, feat_sd=0.1, tau_bias=0.5, viewdir=False):
+    """Seeded inputs of the light-field model for a scene: the per-vertex
+    table [Z_T | Z_C] (N(0, feat_sd^2)) and Xavier decoders (density then
+    colour), with the optical-thickness output bias set to tau_bias."""
+    st = streams(seed + 7919)
+    ct, cc = LF_DECODERS[0], LF_DECODERS[1]
+    F = st["features"].normal(0.0, feat_sd, (n_vertices, ct + cc)).astype(np.float32)
+    wt, wc = lf_widths(viewdir)
+    pt = xavier_params(st["mlp"], wt)
+    pt[-2] = tau_bias
+    return F, np.concatenate([pt, xavier_params(st["mlp"], wc)])
+
+
 @dataclasses.dataclass
 class Scene:
     depth: int

@@ -106,3 +106,39 @@ def test_train_step_full_batch(gpu_lib, paper):
     g = gF.cpu().numpy()
     assert np.all(np.isfinite(g)) and np.abs(g).max() > 0
     assert np.all(np.isfinite(gp.cpu().numpy())) and float(gp.abs().max()) > 0
+
+
+def test_lightfield_train_step_full_batch(gpu_lib, paper):
+    """The two-decoder light-field train step on the full 2^20-ray batch:
+    sampled rays' forward outputs against the oracle, the loss against the
+    step's own outputs, finite gradients in both feature blocks."""
+    import torch
+    from oracle.lightfield import render_lf
+    from synth.configs import lf_inputs
+    w, sc = paper["w"], paper["sc"]
+    F, p = lf_inputs(w.seed, sc.n_vertices)
+    scene = gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    params = torch.from_numpy(p).cuda()
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
+    n = ob.shape[0]
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    gF = torch.zeros_like(scene.features)
+    gp = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    out_rgb = torch.empty((n, 3), device="cuda")
+    out_dep = torch.empty(n, device="cuda")
+    gpu_lib.lf_train_step([scene], [n], params, gpu_lib.make_opts(w.K, "direct", "fp32"), T(ob), T(db),
+                          T(rgb_t), T(dep_t), 0.1, 1.0 / n, [gF], gp, out_rgb=out_rgb, out_depth=out_dep,
+                          loss_out=loss)
+    torch.cuda.synchronize()
+    r, dd = out_rgb.cpu().numpy(), out_dep.cpu().numpy()
+    L_self, _, _ = oracle_loss(r, dd, rgb_t, dep_t, 0.1)
+    assert abs(float(loss.item()) - L_self) <= 1e-4 * abs(L_self)
+    idx = _sample(n, 1024, 4)
+    hits = oracle_trace(paper["oc"], ob[idx], db[idx], w.K)
+    er, ed, _, _ = render_lf(paper["oc"], F, p, (64, 32, 128, 1, 3), ob[idx], db[idx], hits)
+    assert_outputs_close(r[idx], er, 1.0, "lf train-step rgb")
+    assert_outputs_close(dd[idx], ed, max(1.0, np.abs(ed).max()), "lf train-step depth")
+    g = gF.cpu().numpy()
+    assert np.all(np.isfinite(g)) and np.abs(g[:, :64]).max() > 0 and np.abs(g[:, 64:]).max() > 0
+    assert np.all(np.isfinite(gp.cpu().numpy()))
