@@ -216,8 +216,65 @@ def render_lf(octree: Octree, features, params, dec, o, d, hits, tau_mode="direc
     return rgb, depth, acc, st
 
 
-def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None):
-    """Hand-derived backward of ``render_lf``.  Returns (grad_features
+def surface_slots(hits, t_depth):
+    """Per ray, the slot of the hit whose [t_in, t_out) holds the target depth
+    (compared in FP32, the precision of the hit list), or -1 (section 4.4:
+    the voxel containing the surface point seen by the ray)."""
+    _, tin, tout, cnt = hits
+    t = np.asarray(t_depth, np.float32)[:, None]
+    K = tin.shape[1]
+    valid = np.arange(K)[None, :] < cnt[:, None]
+    inside = valid & (tin <= t) & (t < tout)
+    return np.where(inside.any(axis=1), np.argmax(inside, axis=1), -1)
+
+
+def stage_loss(st, hits, rgb, t_rgb, t_depth, kind, lam_eta=1.0, lam_tau=0.0, loss_scale=1.0):
+    """The staged loss of section 4.4 (Eq. 4).  Per ray with a surface voxel
+    v (``surface_slots``), eta* = (t_out - t*) / (t_out - t_in) puts x_s on the
+    target surface point; e_v = e^{-tau_v}.
+      "surface": sum over rays with v of |c_v - c*|^2 + lam_eta (eta_v - eta*)^2
+                 + lam_tau e_v^2;
+      "volume":  sum over rays of |c(r) - c*|^2 plus the same eta and tau terms
+                 of the rays that have v;
+    times loss_scale.  Returns (L, dL/drgb (n, 3), per-hit direct gradients
+    (dL/dc (m, 3), dL/deta (m,), dL/dtau (m,)))."""
+    ls = float(loss_scale)
+    n = st.n
+    t_rgb = np.asarray(t_rgb, np.float64).reshape(n, 3)
+    t_d = np.asarray(t_depth, np.float32).astype(np.float64)
+    slot = surface_slots(hits, t_depth)
+    m = st.ray_i.size
+    hit_of = {(int(r_), int(s_)): i for i, (r_, s_) in enumerate(zip(st.ray_i, st.slot_i))}
+    g_c = np.zeros((m, 3))
+    g_eta = np.zeros(m)
+    g_tau = np.zeros(m)
+    L = 0.0
+    g_rgb = np.zeros((n, 3))
+    if kind == "volume":
+        e = np.asarray(rgb, np.float64) - t_rgb
+        L += ls * np.sum(e * e)
+        g_rgb = 2.0 * ls * e
+    elif kind != "surface":
+        raise ValueError(kind)
+    for r_ in np.nonzero(slot >= 0)[0]:
+        i = hit_of[(int(r_), int(slot[r_]))]
+        t0, t1 = st.t0[i], st.t1[i]
+        eta_gt = (t1 - t_d[r_]) / (t1 - t0)
+        ev = np.exp(-st.tau[r_, slot[r_]])
+        if kind == "surface":
+            ec = st.c[i] - t_rgb[r_]
+            L += ls * np.sum(ec * ec)
+            g_c[i] = 2.0 * ls * ec
+        L += ls * (lam_eta * (st.eta[i] - eta_gt) ** 2 + lam_tau * ev * ev)
+        g_eta[i] = 2.0 * ls * lam_eta * (st.eta[i] - eta_gt)
+        g_tau[i] = -2.0 * ls * lam_tau * ev * ev
+    return L, g_rgb, (g_c, g_eta, g_tau)
+
+
+def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
+    """Hand-derived backward of ``render_lf``.  ``hit_grads`` = per-hit
+    direct gradients (dL/dc, dL/deta, dL/dtau) added to those coming through
+    the compositing (``stage_loss``).  Returns (grad_features
     (n_vertices, C_T + C_C), grad_params)."""
     ct, cc = st.dec[0], st.dec[1]
     rnd = bf16_round if st.bf16 else (lambda v: v)
@@ -237,6 +294,12 @@ def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None):
     ri, si = st.ray_i, st.slot_i
     g_c = w[ri, si][:, None] * g_rgb[ri]                 # dL/dc per hit
     g_ts = w[ri, si] * g_d[ri]                           # dL/dt_s per hit
+    g_tau_hit = g_tau[ri, si]
+    g_eta_direct = np.zeros(ri.size)
+    if hit_grads is not None:
+        g_c = g_c + hit_grads[0]
+        g_eta_direct = hit_grads[1]
+        g_tau_hit = g_tau_hit + hit_grads[2]
     # colour decoder
     gC_out = g_c * st.c * (1.0 - st.c)
     gradsC, g_XC = _mlp_backward(st.lc, st.actsC, st.presC, gC_out, rnd)
@@ -247,10 +310,10 @@ def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None):
     g_us = np.einsum("mja,mj->ma", dw, proj)
     inside = (st.us_raw >= 0.0) & (st.us_raw <= 1.0)
     g_xs = np.where(inside, g_us, 0.0) / st.h            # dL/dx_s
-    g_eta = g_ts * (st.t0 - st.t1) + np.sum(g_xs * (st.x1 - st.x2), axis=1)
+    g_eta = g_ts * (st.t0 - st.t1) + np.sum(g_xs * (st.x1 - st.x2), axis=1) + g_eta_direct
     # density decoder
     gT_out = np.zeros_like(st.oT)
-    gT_out[:, 0] = np.where(st.oT[:, 0] > 0.0, g_tau[ri, si] * st.dtau, 0.0)
+    gT_out[:, 0] = np.where(st.oT[:, 0] > 0.0, g_tau_hit * st.dtau, 0.0)
     gT_out[:, 1] = g_eta * st.eta * (1.0 - st.eta)
     gradsT, g_XT = _mlp_backward(st.lt, st.actsT, st.presT, gT_out, rnd)
     g_z1, g_z2 = g_XT[:, :ct], g_XT[:, ct:2 * ct]

@@ -329,3 +329,120 @@ def test_feature_gradient_conservation():
     r2 = render_lf(oc, Fm, p, dec, o, d, hits)
     fd = (np.sum(g_rgb * (r1[0] - r2[0])) + np.sum(g_dep * (r1[1] - r2[1]))) / (2 * eps)
     assert abs(fd - gF[:, :4].sum(axis=0) @ e) <= 1e-6 * abs(fd) + 1e-8
+
+
+# ------------------------------------------------------------ staged losses (section 4.4)
+
+from oracle.lightfield import stage_loss, surface_slots  # noqa: E402
+
+
+def _const_decoders(s, beta, bc):
+    """Density decoder constant (sigma = s, eta = sigmoid(beta)), colour
+    decoder constant (c = sigmoid(bc)): the dec (2, 3, 4, 1, 1) shapes."""
+    dec = (2, 3, 4, 1, 1)
+    wt, wc = widths_of(dec)
+    lt, lc = _zeros(wt), _zeros(wc)
+    lt[-1][1][:] = [s, beta]
+    lc[-1][1][:] = bc
+    return dec, np.concatenate([_layers_flat(lt), _layers_flat(lc)])
+
+
+@pytest.mark.parametrize("kind", ["surface", "volume"])
+def test_stage_loss_single_voxel_closed_form(kind):
+    oc, h, lo = _one_voxel()
+    s, beta, bc = 0.8, 0.3, np.array([0.2, -0.5, 1.0])
+    dec, p = _const_decoders(s, beta, bc)
+    F = np.zeros((oc.n_vertices, 5))
+    o, d = _axis_ray(h, lo)
+    hits = trace_hits(oc, o, d, 4)
+    rgb, dep, acc, st = render_lf(oc, F, p, dec, o, d, hits)
+    t_star = np.array([2.0 + 0.3 * h], np.float32)      # surface point inside the voxel
+    c_star = np.array([[0.1, 0.7, 0.4]])
+    lam_eta, lam_tau, ls = 0.5, 0.25, 0.125
+    L, g_rgb, hg = stage_loss(st, hits, rgb, c_star, t_star, kind, lam_eta, lam_tau, ls)
+    assert surface_slots(hits, t_star)[0] == 0
+    eta = 1.0 / (1.0 + np.exp(-beta))
+    eta_gt = ((2.0 + h) - float(t_star[0])) / h
+    c = 1.0 / (1.0 + np.exp(-bc))
+    alpha = 1.0 - np.exp(-s)
+    col = c if kind == "surface" else alpha * c
+    L_exp = ls * (np.sum((col - c_star[0]) ** 2) + lam_eta * (eta - eta_gt) ** 2 + lam_tau * np.exp(-2 * s))
+    assert L == pytest.approx(L_exp, rel=1e-12)
+    # gradient of the eta-bias and the tau-bias in closed form
+    _, gp = render_lf_backward(st, g_rgb, np.zeros(1), hit_grads=hg)
+    wt, _ = widths_of(dec)
+    nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
+    assert gp[nt - 1] == pytest.approx(ls * 2 * lam_eta * (eta - eta_gt) * eta * (1 - eta), rel=1e-12)
+    g_s = -2.0 * ls * lam_tau * np.exp(-2 * s)
+    if kind == "volume":                                # d|alpha c - c*|^2 / ds
+        g_s += ls * 2 * np.sum((alpha * c - c_star[0]) * c) * np.exp(-s)
+    assert gp[nt - 2] == pytest.approx(g_s, rel=1e-12)
+    # no surface voxel: a target depth beyond the voxel leaves only the
+    # photometric term of the volume loss
+    L2, _, hg2 = stage_loss(st, hits, rgb, c_star, np.array([5.0], np.float32), kind, lam_eta, lam_tau, ls)
+    assert np.all(hg2[1] == 0) and np.all(hg2[0] == 0)
+    assert L2 == pytest.approx(0.0 if kind == "surface" else ls * np.sum((alpha * c - c_star[0]) ** 2))
+
+
+def test_surface_slots_half_open():
+    tin = np.array([[1.0, 2.0, 0.0]], np.float32)
+    tout = np.array([[2.0, 3.0, 0.0]], np.float32)
+    cnt = np.array([2])
+    hits = (np.array([[0, 1, -1]]), tin, tout, cnt)
+    assert surface_slots(hits, np.array([2.0], np.float32))[0] == 1     # boundary -> the later voxel
+    assert surface_slots(hits, np.array([1.0], np.float32))[0] == 0
+    assert surface_slots(hits, np.array([3.0], np.float32))[0] == -1    # t_out is open
+    assert surface_slots(hits, np.array([0.5], np.float32))[0] == -1
+
+
+@pytest.mark.parametrize("kind", ["surface", "volume"])
+def test_stage_loss_gradients_against_central_differences(kind):
+    oc, F, p, dec, o, d, hits, rgb_t, _ = _fd_case(7, "direct")
+    # target depths: the middle of a random hit of each ray (or none)
+    rng = np.random.default_rng(3)
+    cnt = hits[3]
+    pick = np.where(cnt > 0, rng.integers(0, np.maximum(cnt, 1)), 0)
+    t_d = np.where(cnt > 0, 0.5 * (hits[1][np.arange(o.shape[0]), pick] + hits[2][np.arange(o.shape[0]), pick]),
+                   0.0).astype(np.float32)
+
+    def L(Fx, px):
+        rgb, dep, acc, st = render_lf(oc, Fx, px, dec, o, d, hits)
+        Lv, g_rgb, hg = stage_loss(st, hits, rgb, rgb_t, t_d, kind, 0.7, 0.3, 1.0 / o.shape[0])
+        return Lv, st, g_rgb, hg
+
+    L0, st, g_rgb, hg = L(F, p)
+    assert np.count_nonzero(hg[1]) > 5
+    gF, gp = render_lf_backward(st, g_rgb, np.zeros(o.shape[0]), hit_grads=hg)
+
+    def pattern(sx):
+        return np.concatenate([np.concatenate([z.ravel() > 0 for z in sx.presT + sx.presC]),
+                               sx.oT[:, 0] > 0, ((sx.us_raw >= 0) & (sx.us_raw <= 1)).ravel()])
+
+    base = pattern(st)
+    floor = lambda eps: 64 * np.finfo(np.float64).eps * abs(L0) / eps
+    checked = skipped = 0
+    for _ in range(50):
+        v = np.unique(st.corners)[rng.integers(np.unique(st.corners).size)]
+        c = rng.integers(0, F.shape[1])
+        eps = 1e-6
+        Fp = F.copy(); Fp[v, c] += eps
+        Fm = F.copy(); Fm[v, c] -= eps
+        (Lp, sp, _, _), (Lm, sm, _, _) = L(Fp, p), L(Fm, p)
+        if not (np.array_equal(pattern(sp), base) and np.array_equal(pattern(sm), base)):
+            skipped += 1
+            continue
+        checked += 1
+        g = (Lp - Lm) / (2 * eps)
+        assert abs(g - gF[v, c]) <= 1e-6 * abs(g) + floor(eps), (v, c, g, gF[v, c])
+    for k in rng.choice(p.size, 60, replace=False):
+        eps = 1e-6
+        pp = p.copy(); pp[k] += eps
+        pm = p.copy(); pm[k] -= eps
+        (Lp, sp, _, _), (Lm, sm, _, _) = L(F, pp), L(F, pm)
+        if not (np.array_equal(pattern(sp), base) and np.array_equal(pattern(sm), base)):
+            skipped += 1
+            continue
+        checked += 1
+        g = (Lp - Lm) / (2 * eps)
+        assert abs(g - gp[k]) <= 1e-6 * abs(g) + floor(eps), (k, g, gp[k])
+    assert skipped <= 0.1 * (checked + skipped)
