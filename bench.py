@@ -55,7 +55,7 @@ def bench_lightfield(torch, svlf, timer, args, w, sc, ob_t, db_t, rgb_tt, dep_tt
     rays: train pass (BF16, FP32) and forward render of one view."""
     from synth.configs import lf_inputs
     F, p = lf_inputs(w.seed, sc.n_vertices)
-    scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    scene = svlf.DeviceScene.lf_from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
     params = torch.from_numpy(p).cuda()
     n_b, n_v = ob_t.shape[0], ov_t.shape[0]
     gF = torch.zeros_like(scene.features)

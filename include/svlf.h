@@ -280,8 +280,9 @@ int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* r
  *            SVLF_FLAG_VIEWDIR);
  * composited with Eq. 3 (depth = sum w_i t_s,i).  psi is the trilinear
  * interpolation of the voxel's corner embeddings with u clamped to [0,1].
- * Features: one table per scene, [n_vertices][C_T + C_C] FP32 (Z_T columns
- * first; features_bf16 the same shape in BF16 for the BF16 precision).
+ * Features: one table per scene holding the two collections as blocks, Z_T
+ * [n_vertices][C_T] followed by Z_C [n_vertices][C_C] (FP32; features_bf16
+ * the same layout in BF16 for the BF16 precision); grad_features likewise.
  * params: FP32, F_T's layers then F_C's, each W[out][in] then b[out]
  * (svlf_lf_param_count()).  Supported: C_T = 64, C_C = 32, hidden width
  * 128, one hidden layer in F_T and three in F_C (the paper's sizes, section
@@ -312,7 +313,7 @@ int svlf_lf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ra
                    void* workspace, size_t ws_bytes, void* stream);
 
 /* Backward of svlf_lf_render (re-traces and recomputes); gradients are
- * ADDED to grad_features[s] ([n_vertices][C_T + C_C] FP32, FP32 atomics)
+ * ADDED to grad_features[s] (the features' layout, FP32 atomics)
  * and grad_params (FP32 [svlf_lf_param_count()]); arguments otherwise as
  * svlf_render_backward.  The gradient reaches eta through t_s and through
  * the interpolation at x_s (the clamp of the cell coordinates passes it
@@ -334,6 +335,42 @@ int svlf_lf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t
                        float* out_rgb, float* out_depth, float* loss_out,
                        float* const* grad_features, float* grad_params,
                        void* workspace, size_t ws_bytes, void* stream);
+
+/* The paper's staged training loss (section 4.4, Eq. 4) for the light-field
+ * function.  Per ray with target colour c* and target depth t* (same units
+ * as depth), the surface voxel is the hit whose [t_in, t_out) holds t*
+ * (none if no hit does); its within-voxel depth target is
+ * eta* = (t_out - t*) / (t_out - t_in), the eta that places x_s on the
+ * target surface point.  With e_v = e^{-tau_v} of the surface voxel:
+ *   SVLF_LF_LOSS_SURFACE (voxel training):
+ *     L = loss_scale * sum over rays with a surface voxel v of
+ *         ( |c_v - c*|^2 + lambda_eta (eta_v - eta*)^2 + lambda_tau e_v^2 )
+ *   SVLF_LF_LOSS_VOLUME (volumetric training and fine-tuning):
+ *     L = loss_scale * sum over rays of ( |c(r) - c*|^2
+ *         + [surface voxel v] (lambda_eta (eta_v - eta*)^2 + lambda_tau e_v^2) )
+ *     with c(r) the composited colour (Eq. 3); the paper sets lambda_tau = 0.
+ * freeze_color != 0 leaves the colour embeddings Z_C and the colour decoder
+ * without gradient (the volumetric stage trains the density side only);
+ * the gradient still flows through them to eta. */
+typedef enum { SVLF_LF_LOSS_SURFACE = 1, SVLF_LF_LOSS_VOLUME = 2 } svlf_lf_loss_kind;
+typedef struct {
+  int32_t kind;          /* svlf_lf_loss_kind                                */
+  float lambda_eta;      /* >= 0                                             */
+  float lambda_tau;      /* >= 0                                             */
+  float loss_scale;      /* e.g. 1 / n_rays                                   */
+  int32_t freeze_color;  /* nonzero: no gradients for Z_C and F_C            */
+} svlf_lf_loss;
+
+/* One training pass with a staged loss: render (out_rgb / out_depth
+ * nullable), the loss (loss_out nullable, overwritten) and its gradients,
+ * ADDED to grad_features and grad_params as in svlf_lf_train_step. */
+int svlf_lf_train_stage(const svlf_scene* scenes, int32_t n_scenes,
+                        const int64_t* ray_offsets_host, const svlf_lf_model* model,
+                        const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                        const float* target_rgb, const float* target_depth,
+                        const svlf_lf_loss* loss, float* out_rgb, float* out_depth,
+                        float* loss_out, float* const* grad_features, float* grad_params,
+                        void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- training utilities */
 

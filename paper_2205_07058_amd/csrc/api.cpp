@@ -137,6 +137,7 @@ int make_table(const svlf_scene* scenes, int n_scenes, const int64_t* offs, bool
     d.feat32 = sc.features;
     d.feat16 = sc.features_bf16;
     d.grad = need_grads ? grads[s] : nullptr;
+    d.n_vertices = sc.octree.n_vertices;
     d.ray_begin = offs[s];
     d.ray_end = offs[s + 1];
     d.depth = sc.octree.depth;
@@ -385,6 +386,39 @@ int svlf_lf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
   a.g_acc = grad_acc;
   a.grad_params = grad_params;
   return run_lf_call(kBackward, scenes, n_scenes, ray_offsets_host, model, opts, ray_o, ray_d, a,
+                     grad_features, workspace, ws_bytes, stream, who);
+}
+
+int svlf_lf_train_stage(const svlf_scene* scenes, int32_t n_scenes,
+                        const int64_t* ray_offsets_host, const svlf_lf_model* model,
+                        const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                        const float* target_rgb, const float* target_depth,
+                        const svlf_lf_loss* loss, float* out_rgb, float* out_depth,
+                        float* loss_out, float* const* grad_features, float* grad_params,
+                        void* workspace, size_t ws_bytes, void* stream) {
+  const char* who = "svlf_lf_train_stage";
+  if (loss == nullptr) return fail(SVLF_E_INVAL, who_str(who, "loss is NULL"));
+  if (loss->kind != SVLF_LF_LOSS_SURFACE && loss->kind != SVLF_LF_LOSS_VOLUME)
+    return fail(SVLF_E_RANGE, who_str(who, "unknown loss kind"));
+  if (!(loss->lambda_eta >= 0.0f) || !(loss->lambda_tau >= 0.0f) ||
+      !std::isfinite(loss->lambda_eta) || !std::isfinite(loss->lambda_tau) ||
+      !std::isfinite(loss->loss_scale))
+    return fail(SVLF_E_RANGE, who_str(who, "loss weights must be finite and >= 0"));
+  if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
+  LfArgs a{};
+  a.t_rgb = target_rgb;
+  a.t_depth = target_depth;
+  a.loss_scale = loss->loss_scale;
+  a.loss_kind = loss->kind == SVLF_LF_LOSS_SURFACE ? kLfLossSurface : kLfLossVolume;
+  a.lambda_eta = loss->lambda_eta;
+  a.lambda_tau = loss->lambda_tau;
+  a.freeze_color = loss->freeze_color ? 1 : 0;
+  a.rgb = out_rgb;
+  a.depth = out_depth;
+  a.loss_out = loss_out;
+  a.grad_params = grad_params;
+  return run_lf_call(kTrain, scenes, n_scenes, ray_offsets_host, model, opts, ray_o, ray_d, a,
                      grad_features, workspace, ws_bytes, stream, who);
 }
 

@@ -8,8 +8,10 @@
 // r (and the view direction on request) and outputs the colour; Eq. 3
 // composites front to back.
 //
-// One feature table per scene holds both embeddings per vertex,
-// [Z_T (64) | Z_C (32)].  Decoder inputs are ordered [features | r | (d)].
+// Each scene's feature table holds the two embedding collections as two
+// blocks, Z_T [n_vertices][64] followed by Z_C [n_vertices][32] (so that one
+// of them can be trained or frozen as one contiguous array).  Decoder
+// inputs are ordered [features | r | (d)].
 //
 // Three kernels, all persistent over 256-ray items with ray-aligned hit
 // windows (as the single-decoder kernels):
@@ -39,7 +41,6 @@ using namespace detail;
 
 constexpr int kThreads = 256;
 constexpr int kWaves = 4;
-constexpr int kRow = kLfCT + kLfCC;   // floats per vertex row
 
 // ------------------------------------------------------------ decoder geometry
 
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               if constexpr (BF) {
-                const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * kRow + 8 * q);
+                const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * kLfCT + 8 * q);
                 const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -500,7 +501,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
                   v2[2 * i + 1] += w2[j] * f1;
                 }
               } else {
-                const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * kRow + 4 * q);
+                const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * kLfCT + 4 * q);
                 v1[0] += w1[j] * f.x; v1[1] += w1[j] * f.y; v1[2] += w1[j] * f.z; v1[3] += w1[j] * f.w;
                 v2[0] += w2[j] * f.x; v2[1] += w2[j] * f.y; v2[2] += w2[j] * f.z; v2[3] += w2[j] * f.w;
               }
@@ -679,7 +680,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
             const float g2 = gxs[hh * 2 * kLfCT + kLfCT + lane];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-              unsafeAtomicAdd(sc.grad + static_cast<int64_t>(vid[j]) * kRow + lane, w1[j] * g1 + w2[j] * g2);
+              unsafeAtomicAdd(sc.grad + static_cast<int64_t>(vid[j]) * kLfCT + lane, w1[j] * g1 + w2[j] * g2);
           }
         }
       }
@@ -770,6 +771,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
   const int lb = (G % 8 == 0) ? (bidx % 8) * (G / 8) + bidx / 8 : bidx;
   for (int item = lb; item < a.tab.n_blocks; item += G) {
     const DevScene& sc = a.tab.s[scene_of(a.tab, item)];
+    const int64_t zc = sc.n_vertices * kLfCT;       // Z_C follows Z_T
+    const float* featC32 = sc.feat32 + zc;
+    const uint16_t* featC16 = sc.feat16 != nullptr ? sc.feat16 + zc : nullptr;
+    float* gradC = sc.grad != nullptr ? sc.grad + zc : nullptr;
     const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
     const int64_t r = ray0 + tid;
     const bool live = r < sc.ray_end;
@@ -838,7 +843,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               if constexpr (BF) {
-                const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * kRow + kLfCT + 8 * q);
+                const uint4 raw = *reinterpret_cast<const uint4*>(featC16 + static_cast<int64_t>(vid[j]) * kLfCC + 8 * q);
                 const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -846,7 +851,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
                   v[2 * i + 1] += w[j] * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
                 }
               } else {
-                const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * kRow + kLfCT + 4 * q);
+                const float4 f = *reinterpret_cast<const float4*>(featC32 + static_cast<int64_t>(vid[j]) * kLfCC + 4 * q);
                 v[0] += w[j] * f.x; v[1] += w[j] * f.y; v[2] += w[j] * f.z; v[3] += w[j] * f.w;
               }
             }
@@ -952,9 +957,32 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
         }
         if constexpr (CF::BWD) {
           float gr, gg, gb, gd, ga;
+          // the hit holding the target surface point (staged losses)
+          int surf = -1;
+          float tgt_r = 0.0f, tgt_g = 0.0f, tgt_b = 0.0f;
           if (MODE == kTrain) {
-            const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
-                        eb = cb - a.t_rgb[3 * r + 2], ed = dep - a.t_depth[r];
+            tgt_r = a.t_rgb[3 * r];
+            tgt_g = a.t_rgb[3 * r + 1];
+            tgt_b = a.t_rgb[3 * r + 2];
+          }
+          if (MODE == kTrain && a.loss_kind != kLfLossDefault) {
+            const float ts_ = a.t_depth[r];
+            for (int k = 0; k < count; ++k) {
+              const CRec& rc = rec[p0 + k];
+              if (rc.tin <= ts_ && ts_ < rc.tout) surf = k;
+            }
+          }
+          if (MODE == kTrain && a.loss_kind == kLfLossSurface) {
+            gr = gg = gb = gd = ga = 0.0f;
+          } else if (MODE == kTrain && a.loss_kind == kLfLossVolume) {
+            const float k2 = 2.0f * a.loss_scale;
+            gr = k2 * (cr - tgt_r);
+            gg = k2 * (cg - tgt_g);
+            gb = k2 * (cb - tgt_b);
+            gd = 0.0f;
+            ga = 0.0f;
+          } else if (MODE == kTrain) {
+            const float er = cr - tgt_r, eg = cg - tgt_g, eb = cb - tgt_b, ed = dep - a.t_depth[r];
             const float k2 = a.loss_scale * (2.0f / 3.0f);
             gr = k2 * er;
             gg = k2 * eg;
@@ -969,6 +997,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
             ga = a.g_acc ? a.g_acc[r] : 0.0f;
           }
           float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f, St = 0.0f, Sa = 0.0f;
+          float surf_loss = 0.0f;
           for (int k = count - 1; k >= 0; --k) {
             float* hp = out + 8 * (p0 + k);
             const f32x4 va = *reinterpret_cast<const f32x4*>(hp);
@@ -984,11 +1013,35 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
             Sb += w * c2;
             St += w * ts;
             Sa += w;
+            // direct terms of the staged losses on the surface hit: colour
+            // (surface stage), eta against the target's within-voxel depth,
+            // and the opacity term lambda_tau e^{-2 tau}
+            float gc0 = gr * w, gc1 = gg * w, gc2 = gb * w, gt = gtau, geta = 0.0f;
+            if (k == surf) {
+              const CRec& rc = rec[p0 + k];
+              const float ls2 = 2.0f * a.loss_scale;
+              const float eta_gt = (rc.tout - a.t_depth[r]) / (rc.tout - rc.tin);
+              const float e2 = vb[0] * vb[0];
+              if (a.loss_kind == kLfLossSurface) {
+                gc0 = ls2 * (c0 - tgt_r);
+                gc1 = ls2 * (c1 - tgt_g);
+                gc2 = ls2 * (c2 - tgt_b);
+                surf_loss += (c0 - tgt_r) * (c0 - tgt_r) + (c1 - tgt_g) * (c1 - tgt_g) +
+                             (c2 - tgt_b) * (c2 - tgt_b);
+              }
+              geta = ls2 * a.lambda_eta * (rc.eta - eta_gt);
+              gt -= ls2 * a.lambda_tau * e2;
+              surf_loss += a.lambda_eta * (rc.eta - eta_gt) * (rc.eta - eta_gt) + a.lambda_tau * e2;
+            }
             *reinterpret_cast<f32x4*>(hp) =
-                f32x4{gr * w * c0 * (1.0f - c0), gg * w * c1 * (1.0f - c1), gb * w * c2 * (1.0f - c2),
-                      gtau * vb[1]};
+                f32x4{gc0 * c0 * (1.0f - c0), gc1 * c1 * (1.0f - c1), gc2 * c2 * (1.0f - c2),
+                      gt * vb[1]};
             hp[4] = w * gd;                     // dL/dt_s
+            hp[5] = geta;                       // direct dL/deta
           }
+          // surface-voxel terms of the staged losses (the photometric term
+          // of the volume kind is added for every ray below, hits or not)
+          if (MODE == kTrain && a.loss_kind != kLfLossDefault) loss_acc += a.loss_scale * surf_loss;
         }
       }
 
@@ -1027,13 +1080,13 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
           }
           __syncthreads();
           const El* AT = (l == 0) ? XT : cACT<CF>() + (l - 1) * kLfH * CF::TS;
-          dw_window<BF, M, l, CF::WIN, CF::TS>(GZ, AT, part, wave, lane);
+          if (!a.freeze_color) dw_window<BF, M, l, CF::WIN, CF::TS>(GZ, AT, part, wave, lane);
 #pragma unroll
           for (int bi = 0; bi < CF::NB_PER_T; ++bi) {
             const int b = tid + bi * kThreads;
             const int bl = b < M::NH * kLfH ? b / kLfH : M::NH;
             const int brow = b - bl * kLfH;
-            if (b < M::NBIAS && bl == l && brow < M::out_r(l)) {
+            if (!a.freeze_color && b < M::NBIAS && bl == l && brow < M::out_r(l)) {
               const El* gr_ = GZ + brow * CF::TS;
               float sacc = 0.0f;
               for (int hh = 0; hh < CF::WIN; ++hh) {
@@ -1098,12 +1151,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
               const float gv = gxs[hh * kLfCC + c];
 #pragma unroll
               for (int j = 0; j < 8; ++j) {
-                const int64_t idx = static_cast<int64_t>(vid[j]) * kRow + kLfCT + c;
+                const int64_t idx = static_cast<int64_t>(vid[j]) * kLfCC + c;
                 float fv;
-                if constexpr (BF) fv = bf16_f32(sc.feat16[idx]);
-                else fv = sc.feat32[idx];
+                if constexpr (BF) fv = bf16_f32(featC16[idx]);
+                else fv = featC32[idx];
                 proj[j] = fv * gv;
-                unsafeAtomicAdd(sc.grad + idx, wv[j] * gv);
+                if (!a.freeze_color) unsafeAtomicAdd(gradC + idx, wv[j] * gv);
               }
             } else {
 #pragma unroll
@@ -1138,7 +1191,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
                 gx_d += inside ? gu[ax] * dir[ax] : 0.0f;
               }
               const float* hp = out + 8 * hh;
-              const float g_eta = (rc.tin - rc.tout) * (hp[4] + gx_d * inv_h);
+              const float g_eta = (rc.tin - rc.tout) * (hp[4] + gx_d * inv_h) + hp[5];
               const int mp = hmap[hh];
               const int64_t slot = ray * a.K + (mp >> 16);
               *reinterpret_cast<float2*>(a.gT + 2 * slot) =
@@ -1161,11 +1214,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
         if (a.depth) a.depth[r] = dep;
         if (a.acc) a.acc[r] = acc;
       }
-      if (MODE == kTrain) {
+      if (MODE == kTrain && a.loss_kind == kLfLossDefault) {
         const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
                     eb = cb - a.t_rgb[3 * r + 2], ed = dep - a.t_depth[r];
         loss_acc += a.loss_scale * ((er * er + eg * eg + eb * eb) * (1.0f / 3.0f) +
                                     a.lambda_depth * fabsf(ed));
+      } else if (MODE == kTrain && a.loss_kind == kLfLossVolume) {
+        const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
+                    eb = cb - a.t_rgb[3 * r + 2];
+        loss_acc += a.loss_scale * (er * er + eg * eg + eb * eb);
       }
     }
   }

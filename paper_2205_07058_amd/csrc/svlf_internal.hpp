@@ -23,6 +23,7 @@ struct DevScene {
   const float* feat32;
   const uint16_t* feat16;
   float* grad;            // backward only
+  int64_t n_vertices;
   int64_t ray_begin;      // first ray of this scene
   int64_t ray_end;
   int32_t depth;
@@ -102,6 +103,12 @@ struct LfHit {
   float eta;
 };
 
+// Train-mode losses of the light-field path: the photometric + depth loss of
+// the single-decoder train step, or the paper's staged loss (Eq. 4) on the
+// voxel holding the target surface point (surface stage) or with the
+// composited colour (volumetric stages).
+enum LfLossKind { kLfLossDefault = 0, kLfLossSurface = 1, kLfLossVolume = 2 };
+
 // Supported light-field decoders: C_T = 64, C_C = 32, H = 128, one hidden
 // layer in the density decoder and three in the colour decoder.
 constexpr int kLfCT = 64, kLfCC = 32, kLfH = 128, kLfNHT = 1, kLfNHC = 3;
@@ -136,6 +143,10 @@ struct LfArgs {
   float loss_scale;
   float* loss_out;
   float* grad_params;
+  int32_t loss_kind;      // kLfLoss*: train-mode loss
+  float lambda_eta;       // staged losses: weight of (eta - eta_target)^2
+  float lambda_tau;       // staged losses: weight of e^{-2 tau}
+  int32_t freeze_color;   // nonzero: no gradients for Z_C and the colour decoder
   float* partT;           // [grid][params_density]
   float* partC;           // [grid][params_color]
   float* ws_loss;         // [grid]

@@ -66,6 +66,14 @@ class LfModel(ct.Structure):
                 ("params", ct.c_void_p)]
 
 
+class LfLoss(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("lambda_eta", ct.c_float), ("lambda_tau", ct.c_float),
+                ("loss_scale", ct.c_float), ("freeze_color", ct.c_int32)]
+
+
+LF_LOSS_SURFACE = 1
+LF_LOSS_VOLUME = 2
+
 # The light-field decoders the library supports (the paper's sizes):
 # (C_T, C_C, hidden, hidden layers of F_T, hidden layers of F_C)
 LF_DECODERS = (64, 32, 128, 1, 3)
@@ -115,6 +123,11 @@ _SIGS = {
                             ct.c_void_p, ct.c_void_p, ct.c_float, ct.c_float, ct.c_void_p,
                             ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                             ct.c_size_t, ct.c_void_p], ct.c_int),
+    "svlf_lf_train_stage": ([ct.POINTER(Scene), ct.c_int32, ct.POINTER(ct.c_int64),
+                             ct.POINTER(LfModel), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_void_p,
+                             ct.c_void_p, ct.c_void_p, ct.POINTER(LfLoss), ct.c_void_p, ct.c_void_p,
+                             ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                             ct.c_void_p], ct.c_int),
     "svlf_to_bf16": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_fill": ([ct.c_void_p, ct.c_float, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_mlp_forward": ([ct.POINTER(Mlp), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_int64,
@@ -313,6 +326,21 @@ class DeviceScene:
         if features.shape[0] != oc.n_vertices:
             raise ValueError(f"features has {features.shape[0]} rows, octree has {oc.n_vertices} vertices")
         f = torch.from_numpy(np.ascontiguousarray(features, np.float32)).to(device)
+        sc = cls(oc, f)
+        if bf16:
+            sc.refresh_bf16()
+        return sc
+
+    @classmethod
+    def lf_from_host(cls, leaf_ijk, depth, features: np.ndarray, bf16=True, device="cuda"):
+        """Scene for the light-field functions: features given per vertex as
+        [n_vertices][C_T + C_C], stored on the device in the library's block
+        layout (a flat array: Z_T block, then Z_C block)."""
+        torch = _torch()
+        oc = DeviceOctree(leaf_ijk, depth, device)
+        if features.shape != (oc.n_vertices, LF_DECODERS[0] + LF_DECODERS[1]):
+            raise ValueError(f"features must be [{oc.n_vertices}][{LF_DECODERS[0] + LF_DECODERS[1]}]")
+        f = torch.from_numpy(lf_feature_blocks(features)).to(device)
         sc = cls(oc, f)
         if bf16:
             sc.refresh_bf16()
@@ -607,3 +635,53 @@ def lf_train_step(scenes, ray_counts, params, opts: RenderOpts, ray_o, ray_d, ta
                                      _grad_ptrs(grad_features),
                                      _ptr(grad_params, torch.float32, tuple(params.shape), "grad_params"),
                                      _ptr(ws, torch.uint8), nb, _stream()))
+
+
+def make_lf_loss(kind, lambda_eta=1.0, lambda_tau=0.0, loss_scale=1.0, freeze_color=False) -> LfLoss:
+    k = {"surface": LF_LOSS_SURFACE, "volume": LF_LOSS_VOLUME}.get(kind, kind)
+    return LfLoss(int(k), float(lambda_eta), float(lambda_tau), float(loss_scale),
+                  1 if freeze_color else 0)
+
+
+def lf_train_stage(scenes, ray_counts, params, opts: RenderOpts, ray_o, ray_d, target_rgb,
+                   target_depth, loss: LfLoss, grad_features, grad_params, out_rgb=None,
+                   out_depth=None, loss_out=None, workspace: Workspace = None):
+    torch = _torch()
+    scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
+    arr, offs, n = _scene_array(scenes, ray_counts)
+    m = make_lf_model()
+    m.params = _lf_params(params, opts)
+    nb = lf_workspace_bytes(opts, n)
+    ws = (workspace or _default_ws).get(nb, ray_o.device)
+    for g, s in zip(grad_features, scenes):
+        _ptr(g, torch.float32, tuple(s.features.shape), "grad_features")
+    _check("svlf_lf_train_stage",
+           load().svlf_lf_train_stage(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),
+                                      _ptr(ray_o, torch.float32, (n, 3), "ray_o"),
+                                      _ptr(ray_d, torch.float32, (n, 3), "ray_d"),
+                                      _ptr(target_rgb, torch.float32, (n, 3), "target_rgb"),
+                                      _ptr(target_depth, torch.float32, (n,), "target_depth"),
+                                      ct.byref(loss),
+                                      _ptr(out_rgb, torch.float32, (n, 3), "out_rgb", allow_none=True),
+                                      _ptr(out_depth, torch.float32, (n,), "out_depth", allow_none=True),
+                                      _ptr(loss_out, torch.float32, (1,), "loss_out", allow_none=True),
+                                      _grad_ptrs(grad_features),
+                                      _ptr(grad_params, torch.float32, tuple(params.shape), "grad_params"),
+                                      _ptr(ws, torch.uint8), nb, _stream()))
+
+
+def lf_feature_blocks(features: np.ndarray) -> np.ndarray:
+    """[n_vertices][C_T + C_C] per-vertex rows -> the library's block layout
+    (Z_T [n][C_T] then Z_C [n][C_C]) as one flat FP32 array."""
+    ct_ = LF_DECODERS[0]
+    f = np.asarray(features, np.float32)
+    return np.concatenate([np.ascontiguousarray(f[:, :ct_]).ravel(),
+                           np.ascontiguousarray(f[:, ct_:]).ravel()])
+
+
+def lf_feature_rows(blocks, n_vertices) -> np.ndarray:
+    """Inverse of lf_feature_blocks."""
+    ct_, cc_ = LF_DECODERS[0], LF_DECODERS[1]
+    b = np.asarray(blocks, np.float32).ravel()
+    return np.concatenate([b[:n_vertices * ct_].reshape(n_vertices, ct_),
+                           b[n_vertices * ct_:].reshape(n_vertices, cc_)], axis=1)

@@ -153,8 +153,12 @@ class LfCase:
         self.p = np.ascontiguousarray(params, np.float32)
         assert self.p.size == n_params(self.dec, viewdir)
         self.oc = Octree(leaf_ijk, depth)
-        self.scene = svlf.DeviceScene.from_host(leaf_ijk, depth, self.F, bf16=True)
+        self.scene = svlf.DeviceScene.lf_from_host(leaf_ijk, depth, self.F, bf16=True)
         self.params = torch.from_numpy(self.p).cuda()
+
+    def rows(self, g):
+        """Device feature gradient (block layout) -> [n_vertices][C_T + C_C]."""
+        return self.svlf.lf_feature_rows(g.cpu().numpy() if hasattr(g, "cpu") else g, self.F.shape[0])
 
     @classmethod
     def random(cls, svlf, seed, depth, n_obj=3, feat_sd=0.5, sigma_bias=0.5, K=8, tau_mode="direct",
@@ -205,7 +209,7 @@ class LfCase:
                                      to, td, t(g_rgb), t(g_dep), None if g_acc is None else t(g_acc),
                                      [gF], gp)
         torch.cuda.synchronize()
-        return gF.cpu().numpy(), gp.cpu().numpy()
+        return self.rows(gF), gp.cpu().numpy()
 
     def smooth_rays(self, o, d, margin=1e-4):
         """Rays none of whose hits is within `margin` of a kink: a ReLU input

@@ -94,7 +94,7 @@ def test_lf_train_step_fp32(gpu_lib):
         assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L), name
         assert_outputs_close(out_rgb.cpu().numpy(), er, 1.0, f"{name} train rgb")
         assert_outputs_close(out_dep.cpu().numpy(), ed, max(1.0, np.abs(ed).max()), f"{name} train depth")
-        assert_grad_close(gF.cpu().numpy(), eF, f"{name} train grad_features")
+        assert_grad_close(case.rows(gF), eF, f"{name} train grad_features")
         assert_grad_close(gp.cpu().numpy(), ep, f"{name} train grad_params", rel_nw=1e-4, rel_el=None)
 
 
@@ -111,3 +111,59 @@ def test_lf_backward_bf16(gpu_lib):
         cos = lambda a, b: float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
         assert cos(gF, eF) > 0.999 and cos(gp, ep) > 0.999, (name, cos(gF, eF), cos(gp, ep))
         assert np.linalg.norm(gF - eF) <= 0.05 * np.linalg.norm(eF), name
+
+
+def _stage_targets(case, o, d, seed):
+    """Target colours and depths: each ray's target surface point in the
+    middle of one of its hits (so most rays have a surface voxel)."""
+    from oracle.trace import trace_hits
+    rng = np.random.default_rng(seed)
+    hits = trace_hits(case.oc, o, d, case.K)
+    cnt = hits[3]
+    pick = np.where(cnt > 0, rng.integers(0, np.maximum(cnt, 1)), 0)
+    idx = np.arange(o.shape[0])
+    t_d = np.where(cnt > 0, 0.5 * (hits[1][idx, pick] + hits[2][idx, pick]), 0.0).astype(np.float32)
+    return rng.uniform(0, 1, (o.shape[0], 3)).astype(np.float32), t_d, hits
+
+
+@pytest.mark.parametrize("kind,freeze", [("surface", False), ("volume", False), ("volume", True)])
+def test_lf_train_stage_fp32(gpu_lib, kind, freeze):
+    """The staged loss of section 4.4 (Eq. 4): loss value and gradients
+    against the oracle; with the colour side frozen its gradients are zero and
+    the density side's are unchanged."""
+    import torch
+    from oracle.lightfield import stage_loss
+    case = LfCase.random(gpu_lib, 84, 5, n_obj=3, K=8)
+    rng = np.random.default_rng(31)
+    o, d = random_rays(rng, 2500, inside_frac=0.0)
+    keep = case.smooth_rays(o, d)
+    o, d = o[keep], d[keep]
+    n = o.shape[0]
+    t_rgb, t_d, hits = _stage_targets(case, o, d, 5)
+    lam_eta, lam_tau, ls = 0.7, 0.2, 1.0 / n
+    to, td = case.rays(o, d)
+    gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+    gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+    loss_t = torch.zeros(1, dtype=torch.float32, device="cuda")
+    loss = gpu_lib.make_lf_loss(kind, lam_eta, lam_tau, ls, freeze)
+    case.svlf.lf_train_stage([case.scene], [n], case.params, case.opts(), to, td,
+                             torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_d).cuda(), loss,
+                             [gF], gp, loss_out=loss_t)
+    torch.cuda.synchronize()
+    rgb, _, _, st = case.oracle(o, d)
+    L, g_rgb, hg = stage_loss(st, hits, rgb, t_rgb, t_d, kind, lam_eta, lam_tau, ls)
+    eF, ep = render_lf_backward(st, g_rgb, np.zeros(n), hit_grads=hg)
+    assert np.count_nonzero(hg[1]) > 100
+    assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L)
+    ct = case.dec[0]
+    from oracle.lightfield import widths_of
+    wt, _ = widths_of(case.dec)
+    nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
+    gFr, gpn = case.rows(gF), gp.cpu().numpy()
+    assert_grad_close(gFr[:, :ct], eF[:, :ct], f"{kind} grad Z_T")
+    assert_grad_close(gpn[:nt], ep[:nt], f"{kind} grad F_T", rel_nw=1e-4, rel_el=None)
+    if freeze:
+        assert np.all(gFr[:, ct:] == 0) and np.all(gpn[nt:] == 0)
+    else:
+        assert_grad_close(gFr[:, ct:], eF[:, ct:], f"{kind} grad Z_C")
+        assert_grad_close(gpn[nt:], ep[nt:], f"{kind} grad F_C", rel_nw=1e-4, rel_el=None)

@@ -117,7 +117,7 @@ def test_lightfield_train_step_full_batch(gpu_lib, paper):
     from synth.configs import lf_inputs
     w, sc = paper["w"], paper["sc"]
     F, p = lf_inputs(w.seed, sc.n_vertices)
-    scene = gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    scene = gpu_lib.DeviceScene.lf_from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
     params = torch.from_numpy(p).cuda()
     ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
     n = ob.shape[0]
@@ -139,6 +139,6 @@ def test_lightfield_train_step_full_batch(gpu_lib, paper):
     er, ed, _, _ = render_lf(paper["oc"], F, p, (64, 32, 128, 1, 3), ob[idx], db[idx], hits)
     assert_outputs_close(r[idx], er, 1.0, "lf train-step rgb")
     assert_outputs_close(dd[idx], ed, max(1.0, np.abs(ed).max()), "lf train-step depth")
-    g = gF.cpu().numpy()
+    g = gpu_lib.lf_feature_rows(gF.cpu().numpy(), sc.n_vertices)
     assert np.all(np.isfinite(g)) and np.abs(g[:, :64]).max() > 0 and np.abs(g[:, 64:]).max() > 0
     assert np.all(np.isfinite(gp.cpu().numpy()))
