@@ -113,3 +113,27 @@ class Octree:
         first = np.searchsorted(nxt, parent_codes << 3)
         last = np.searchsorted(nxt, (parent_codes << 3) + 8)
         return first, last
+
+
+def occupancy_from_depth(o, d, t, depth):
+    """Occupied leaves of a depth-`depth` grid from depth maps (section 4.1:
+    the octree keeps the voxels that contain a surface; the surface points
+    come from the dataset's depth).  For every ray with a finite target
+    depth t > 0 the surface point p = o + t d is taken in binary32
+    arithmetic (a product, then a sum, each rounded to nearest; no fused
+    multiply-add) and its cell is floor(RN(p + 1) * 2^(depth-1)) per axis;
+    points outside [0, 2^depth) on any axis are dropped.  Returns the unique
+    cells, int64 (m, 3), in ascending Morton order (the leaf-id order)."""
+    o = np.asarray(o, np.float32)
+    d = np.asarray(d, np.float32)
+    t = np.asarray(t, np.float32)
+    ok = np.isfinite(t) & (t > np.float32(0))
+    with np.errstate(invalid="ignore", over="ignore"):
+        p = o + t[:, None] * d                       # numpy float32: RN product, RN sum
+        q = (p + np.float32(1.0)) * np.float32(2.0 ** (depth - 1))
+    ok &= np.all(np.isfinite(q), axis=1) & np.all((q >= 0) & (q < (1 << depth)), axis=1)
+    cells = np.floor(q[ok]).astype(np.int64)
+    if cells.shape[0] == 0:
+        return np.zeros((0, 3), np.int64)
+    codes = np.unique(morton_encode(cells, depth))
+    return morton_decode(codes, depth)

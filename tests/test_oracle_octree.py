@@ -68,3 +68,59 @@ def test_rejects_bad_input():
         Octree([[0, 0, 0], [0, 0, 0]], 2)
     with pytest.raises(ValueError):
         Octree([[0, 0, 0]], 0)
+
+
+# ------------------------------------------------------------ occupancy from depth maps
+
+def test_occupancy_from_depth_hand_cases():
+    from oracle.octree import occupancy_from_depth
+    L = 2                                            # cells of edge 0.5, 4 per axis
+    d = np.array([[1, 0, 0]] * 7, np.float32)
+    o = np.array([[-3, 0.1, 0.1],      # p = (0, .1, .1): on a face -> the upper cell
+                  [-3, -0.9, 0.6],     # p = (0, -.9, .6)
+                  [-4, 0.1, 0.1],      # p = (-1, .1, .1): the lowest cell on x
+                  [-2, 0.1, 0.1],      # p = (1, .1, .1): outside (upper bound open)
+                  [-3, 0.1, 0.1],      # t = 0: no surface
+                  [-3, 0.1, 0.1],      # duplicate of the first
+                  [-3, 0.1, 0.1]],     # t = NaN
+                 np.float32)
+    t = np.array([3, 3, 3, 3, 0, 3, np.nan], np.float32)
+    got = occupancy_from_depth(o, d, t, L)
+    exp = {(2, 2, 2), (2, 0, 3), (0, 2, 2)}
+    assert {tuple(c) for c in got.tolist()} == exp and got.shape[0] == 3
+    # Morton order: codes ascending
+    from oracle.octree import morton_encode
+    codes = morton_encode(got, L)
+    assert np.all(np.diff(codes) > 0)
+
+
+def test_occupancy_from_depth_scalar_rational_reference():
+    """Per-point scalar reference: q = RN32(RN32(o + RN32(t d)) + 1) 2^(L-1)
+    floored with exact rational arithmetic."""
+    from fractions import Fraction
+    from oracle.octree import occupancy_from_depth
+    rng = np.random.default_rng(0)
+    L = 4
+    n = 400
+    o = rng.uniform(-1.2, 1.2, (n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3)).astype(np.float32)
+    t = rng.uniform(0, 0.3, n).astype(np.float32)
+    # points exactly on cell faces: x = 0.25 k
+    o[:40, 0] = (rng.integers(-4, 4, 40) * 0.25).astype(np.float32)
+    d[:40, 0] = 0.0
+    t[::17] = 0
+    cells = set()
+    for r in range(n):
+        if not t[r] > 0:
+            continue
+        c = []
+        for a in range(3):
+            p = np.float32(o[r, a]) + np.float32(np.float32(t[r]) * np.float32(d[r, a]))
+            q = Fraction(float(np.float32(p) + np.float32(1.0))) * (2 ** (L - 1))
+            i = q.numerator // q.denominator
+            c.append(i)
+        if all(0 <= i < (1 << L) for i in c):
+            cells.add(tuple(c))
+    got = occupancy_from_depth(o, d, t, L)
+    assert {tuple(c) for c in got.tolist()} == cells
+    assert len(cells) > 20
