@@ -103,7 +103,7 @@ def parse():
                     help="rays of the batch the oracle trains on for the CPU baseline")
     ap.add_argument("--psnr-rays", type=int, default=16384)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,lf,copy,"
+                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,lf,occ,copy,"
                          "multi (the ragged 8-scene workload; not in 'all')")
     return ap.parse_args()
 
@@ -141,7 +141,7 @@ def main():
     from synth.configs import get_config
 
     sections = set(args.sections.split(",")) if args.sections != "all" else {
-        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr", "lf"}
+        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr", "lf", "occ"}
     torch.cuda.set_device(0)
     svlf.load()
     t0 = time.time()
@@ -237,6 +237,18 @@ def main():
     if "lf" in sections:
         res["lightfield"] = bench_lightfield(torch, svlf, timer, args, w, sc, ob_t, db_t, rgb_tt,
                                              dep_tt, ov_t, dv_t, hits_b, hits_v)
+
+    if "occ" in sections:
+        # occupied leaves from the depth map of one view (section 4.1)
+        _, dep_v = w.targets(o_v, d_v)
+        dep_vt = T(dep_v)
+        f = lambda: svlf.occupancy_from_depth(ov_t, dv_t, dep_vt, sc.depth)
+        ms, _ = timer.run(f, args.steps, args.warmup)
+        n_leaf = int(f().shape[0])
+        res["occupancy"] = {"ms_per_view": round(ms / args.steps, 4),
+                            "rays_per_s": round(n_v * args.steps / ms * 1e3, 1),
+                            "leaves": n_leaf, "level": sc.depth}
+        log(f"occupancy from one depth map: {ms / args.steps:.3f} ms, {n_leaf} leaves")
 
     if "copy" in sections:
         # a plain device copy of known size: calibrates the HBM byte counters
@@ -340,6 +352,7 @@ def main():
         if "step_lazy_adam_ms" in res else None,
         "feature_rows_touched_per_batch": round(res["touched_rows"], 4) if "touched_rows" in res else None,
         "lightfield": res.get("lightfield"),
+        "occupancy_from_depth": res.get("occupancy"),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
         "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
         "device_copy_gbs": round(res["copy_gbs"], 1) if "copy_gbs" in res else None,

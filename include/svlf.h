@@ -10,6 +10,7 @@
  * feature interpolated at the middle of the ray's segment in the voxel:
  *
  *   svlf_build_octree   sparse octree over occupied leaves (section 4.1)
+ *   svlf_occupancy_from_depth  occupied leaves from depth maps (section 4.1)
  *   svlf_trace_hits     first K leaves crossed by each ray (sections 4.2-4.3)
  *   svlf_render         traversal + trilinear features + MLP + Eq. 3
  *   svlf_render_backward  gradients of rgb/depth/acc w.r.t. the features and
@@ -184,6 +185,27 @@ typedef struct {
  * Section 4.1 ("Scene volume"). */
 int svlf_build_octree_sizes(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
                             svlf_octree_sizes* out);
+
+/* Workspace bytes of svlf_occupancy_from_depth at grid level `level`
+ * (1..10): a bitmap of 8^level bits and per-block counts (0 if out of
+ * range). */
+size_t svlf_occupancy_workspace_bytes(int32_t level);
+
+/* Occupied leaves from depth maps (section 4.1: the octree keeps the voxels
+ * that contain a surface, found from the depth the dataset provides).  For
+ * every ray r with a finite target depth t[r] > 0 the surface point
+ * p = o + t d is computed in binary32 (rounded product, then rounded sum,
+ * no fused multiply-add) and its leaf at `level` is
+ * floor(RN(p + 1) * 2^(level-1)) per axis; points outside the grid are
+ * dropped.  ray_o, ray_d: device FP32 [n][3]; target_depth: device FP32 [n].
+ * leaf_ijk_out: device int32 [n][3] (capacity n; a ray marks at most one
+ * leaf) receives the unique leaves in ascending Morton order (leaf-id
+ * order), n_leaves_out (device int64) their number.  Feed the leaves to
+ * svlf_build_octree (host copy).  Asynchronous on `stream`. */
+int svlf_occupancy_from_depth(const float* ray_o, const float* ray_d, const float* target_depth,
+                              int64_t n, int32_t level, int32_t* leaf_ijk_out,
+                              int64_t* n_leaves_out, void* workspace, size_t ws_bytes,
+                              void* stream);
 
 /* Builds the octree on the host and copies it to the device arrays
  * nodes_dev (n_nodes entries) and leaf_corners_dev (n_leaves*8 entries), sized

@@ -502,6 +502,40 @@ int svlf_build_octree_host(const int32_t* leaf_ijk_host, int64_t n, int32_t dept
   return SVLF_OK;
 }
 
+size_t svlf_occupancy_workspace_bytes(int32_t level) {
+  if (level < 1 || level > SVLF_MAX_DEPTH) {
+    fail(SVLF_E_RANGE, "svlf_occupancy_workspace_bytes: level must be in [1, 10]");
+    return 0;
+  }
+  const size_t words = occupancy_bitmap_words(level);
+  return align256(words * sizeof(uint32_t)) + align256((words / 256) * sizeof(int));
+}
+
+int svlf_occupancy_from_depth(const float* ray_o, const float* ray_d, const float* target_depth,
+                              int64_t n, int32_t level, int32_t* leaf_ijk_out,
+                              int64_t* n_leaves_out, void* workspace, size_t ws_bytes,
+                              void* stream) {
+  const char* who = "svlf_occupancy_from_depth";
+  if (level < 1 || level > SVLF_MAX_DEPTH)
+    return fail(SVLF_E_RANGE, who_str(who, "level must be in [1, 10]"));
+  if (n < 0) return fail(SVLF_E_INVAL, who_str(who, "n < 0"));
+  if (n_leaves_out == nullptr) return fail(SVLF_E_INVAL, who_str(who, "n_leaves_out is NULL"));
+  if (n > 0 && (ray_o == nullptr || ray_d == nullptr || target_depth == nullptr ||
+                leaf_ijk_out == nullptr))
+    return fail(SVLF_E_INVAL, who_str(who, "NULL array"));
+  const size_t need = svlf_occupancy_workspace_bytes(level);
+  if (workspace == nullptr || ws_bytes < need)
+    return fail(SVLF_E_WORKSPACE, who_str(who, "workspace missing or smaller than svlf_occupancy_workspace_bytes()"));
+  const size_t words = occupancy_bitmap_words(level);
+  char* base = static_cast<char*>(workspace);
+  hipError_t e = launch_occupancy(ray_o, ray_d, target_depth, n, level,
+                                  reinterpret_cast<uint32_t*>(base),
+                                  reinterpret_cast<int*>(base + align256(words * sizeof(uint32_t))),
+                                  leaf_ijk_out, n, n_leaves_out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, who);
+  return SVLF_OK;
+}
+
 int svlf_trace_hits(const svlf_octree* oct, const float* ray_o, const float* ray_d,
                     int64_t n_rays, int32_t K, int32_t* hit_leaf, float* hit_tin,
                     float* hit_tout, int32_t* hit_count, void* stream) {

@@ -152,6 +152,12 @@ struct LfArgs {
   float* ws_loss;         // [grid]
 };
 
+// Occupied leaves from depth maps (occupancy.hip).
+size_t occupancy_bitmap_words(int level);
+hipError_t launch_occupancy(const float* o, const float* d, const float* t, int64_t n, int level,
+                            uint32_t* bitmap, int* counts, int32_t* leaf_ijk, int64_t cap,
+                            int64_t* n_out, hipStream_t s);
+
 // Runs packing, the density kernel, the colour kernel and (backward / train)
 // the density backward and the reductions of the decoder gradients.
 hipError_t launch_lf(const LfArgs& a, int mode, hipStream_t s);

@@ -128,6 +128,10 @@ _SIGS = {
                              ct.c_void_p, ct.c_void_p, ct.POINTER(LfLoss), ct.c_void_p, ct.c_void_p,
                              ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t,
                              ct.c_void_p], ct.c_int),
+    "svlf_occupancy_workspace_bytes": ([ct.c_int32], ct.c_size_t),
+    "svlf_occupancy_from_depth": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
+                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p],
+                                  ct.c_int),
     "svlf_to_bf16": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_fill": ([ct.c_void_p, ct.c_float, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_mlp_forward": ([ct.POINTER(Mlp), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_int64,
@@ -685,3 +689,23 @@ def lf_feature_rows(blocks, n_vertices) -> np.ndarray:
     b = np.asarray(blocks, np.float32).ravel()
     return np.concatenate([b[:n_vertices * ct_].reshape(n_vertices, ct_),
                            b[n_vertices * ct_:].reshape(n_vertices, cc_)], axis=1)
+
+
+def occupancy_from_depth(ray_o, ray_d, target_depth, level):
+    """Occupied leaves (device int32 [m][3], Morton order) of the depth maps'
+    surface points at grid level `level`."""
+    torch = _torch()
+    n = ray_o.shape[0]
+    nb = load().svlf_occupancy_workspace_bytes(int(level))
+    if nb == 0:
+        raise SvlfError("svlf_occupancy_workspace_bytes", E_RANGE, last_error())
+    ws = torch.empty(nb, dtype=torch.uint8, device=ray_o.device)
+    out = torch.empty((max(n, 1), 3), dtype=torch.int32, device=ray_o.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=ray_o.device)
+    _check("svlf_occupancy_from_depth",
+           load().svlf_occupancy_from_depth(_ptr(ray_o, torch.float32, (n, 3), "ray_o"),
+                                            _ptr(ray_d, torch.float32, (n, 3), "ray_d"),
+                                            _ptr(target_depth, torch.float32, (n,), "target_depth"),
+                                            n, int(level), _ptr(out), _ptr(cnt), _ptr(ws), nb,
+                                            _stream()))
+    return out[:int(cnt.item())]

@@ -234,3 +234,19 @@ def test_lf_validation(lib):
     need = lib.svlf_lf_workspace_bytes(ct.byref(m), ct.byref(opts), 100)
     assert need > 100 * 8 * (16 + 32 + 8)
     assert call(m, ct.c_void_p(0x100), need - 1) == svlf.E_WORKSPACE
+
+
+def test_occupancy_validation(lib):
+    assert lib.svlf_occupancy_workspace_bytes(0) == 0
+    assert lib.svlf_occupancy_workspace_bytes(11) == 0
+    assert lib.svlf_occupancy_workspace_bytes(1) > 0
+    assert lib.svlf_occupancy_workspace_bytes(10) >= (1 << 30) // 8
+    f = lib.svlf_occupancy_from_depth
+    cnt = ct.c_void_p(0x100)
+    assert f(None, None, None, 10, 0, None, cnt, None, 0, None) == svlf.E_RANGE
+    assert f(None, None, None, -1, 5, None, cnt, None, 0, None) == svlf.E_INVAL
+    assert f(None, None, None, 10, 5, None, cnt, None, 0, None) == svlf.E_INVAL
+    assert f(None, None, None, 10, 5, None, None, None, 0, None) == svlf.E_INVAL
+    p = ct.c_void_p(0x100)
+    need = lib.svlf_occupancy_workspace_bytes(5)
+    assert f(p, p, p, 10, 5, p, cnt, p, need - 1, None) == svlf.E_WORKSPACE
