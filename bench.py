@@ -103,7 +103,7 @@ def parse():
                     help="rays of the batch the oracle trains on for the CPU baseline")
     ap.add_argument("--psnr-rays", type=int, default=16384)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,lf,occ,copy,"
+                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,lf,occ,det,copy,"
                          "multi (the ragged 8-scene workload; not in 'all')")
     return ap.parse_args()
 
@@ -141,7 +141,7 @@ def main():
     from synth.configs import get_config
 
     sections = set(args.sections.split(",")) if args.sections != "all" else {
-        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr", "lf", "occ"}
+        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr", "lf", "occ", "det"}
     torch.cuda.set_device(0)
     svlf.load()
     t0 = time.time()
@@ -263,6 +263,13 @@ def main():
     if "multi" in sections:
         multi = bench_multi(torch, svlf, timer, args)
 
+    if "det" in sections:
+        # the same BF16 train step with the deterministic feature-gradient reduction
+        ms, _ = timer.run(train_fn("bf16", svlf.FLAG_DETERMINISTIC), args.steps, args.warmup)
+        res["train_bf16_det_ms"] = ms / args.steps
+        log(f"train step bf16, deterministic feature gradient: {ms / args.steps:.3f} ms/step, "
+            f"{n_b * args.steps / ms * 1e3 / 1e6:.1f} M rays/s")
+
     stages = {}
     if "stages" in sections:
         # split one BF16 train step into its kernels with events between them
@@ -353,6 +360,8 @@ def main():
         "feature_rows_touched_per_batch": round(res["touched_rows"], 4) if "touched_rows" in res else None,
         "lightfield": res.get("lightfield"),
         "occupancy_from_depth": res.get("occupancy"),
+        "train_bf16_deterministic_rays_per_s": round(n_b / (res["train_bf16_det_ms"] * 1e-3), 1)
+        if "train_bf16_det_ms" in res else None,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
         "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
         "device_copy_gbs": round(res["copy_gbs"], 1) if "copy_gbs" in res else None,

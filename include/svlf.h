@@ -177,6 +177,14 @@ typedef struct {
  * decoders 11-32-32-4 and 35-64-64-64-4.  The direction takes no gradient;
  * grad_features keep C columns. */
 #define SVLF_FLAG_VIEWDIR 4
+/* SVLF_FLAG_DETERMINISTIC (svlf_render_backward, svlf_train_step; one scene):
+ * the feature gradient is reduced in a fixed order instead of with FP32
+ * atomics, so repeated calls on the same inputs give bit-identical
+ * gradients.  The backward keeps (u, dL/dx) per hit; the hits are bucketed
+ * by leaf (counting sort, each bucket in ascending hit-slot order) and every
+ * vertex sums over its up to 8 adjacent leaves in a fixed order.  The
+ * workspace must then come from svlf_workspace_bytes_scenes. */
+#define SVLF_FLAG_DETERMINISTIC 8
 
 /* ---------------------------------------------------------------- octree */
 
@@ -267,6 +275,12 @@ int svlf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
                          const float* grad_rgb, const float* grad_depth, const float* grad_acc,
                          float* const* grad_features, float* grad_params,
                          void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for calls over these scenes (the scene sizes matter with
+ * SVLF_FLAG_DETERMINISTIC; otherwise equal to svlf_workspace_bytes).
+ * 0 on invalid arguments. */
+size_t svlf_workspace_bytes_scenes(const svlf_mlp* mlp, const svlf_render_opts* opts,
+                                   const svlf_scene* scenes, int32_t n_scenes, int64_t n_rays);
 
 /* One fused training pass: render, loss
  *   L = sum over rays of ( |rgb - rgb*|^2 / 3 + lambda_depth |depth - depth*| ) * loss_scale

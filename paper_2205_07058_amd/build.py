@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsvlf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "octree_build.cpp", "trace.hip", "shade.hip", "lf.hip", "occupancy.hip", "util.hip"]
+SOURCES = ["api.cpp", "octree_build.cpp", "trace.hip", "shade.hip", "lf.hip", "occupancy.hip", "detgrad.hip", "util.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-function"]

@@ -97,7 +97,8 @@ int check_opts(const svlf_render_opts* opts, const char* who) {
     return fail(SVLF_E_RANGE, who_str(who, "unknown tau_mode"));
   if (opts->precision != SVLF_FP32 && opts->precision != SVLF_BF16)
     return fail(SVLF_E_RANGE, who_str(who, "unknown precision"));
-  if (opts->flags & ~(SVLF_FLAG_TRACE_ONLY | SVLF_FLAG_REUSE_HITS | SVLF_FLAG_VIEWDIR))
+  if (opts->flags &
+      ~(SVLF_FLAG_TRACE_ONLY | SVLF_FLAG_REUSE_HITS | SVLF_FLAG_VIEWDIR | SVLF_FLAG_DETERMINISTIC))
     return fail(SVLF_E_INVAL, who_str(who, "unknown flags"));
   if ((opts->flags & SVLF_FLAG_TRACE_ONLY) && (opts->flags & SVLF_FLAG_REUSE_HITS))
     return fail(SVLF_E_INVAL, who_str(who, "TRACE_ONLY and REUSE_HITS exclude each other"));
@@ -172,6 +173,20 @@ WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
   return w;
 }
 
+// Deterministic mode: [per-hit (u, dL/dx) records][reduction scratch] after
+// the standard layout.
+struct DetExtra {
+  size_t gxu, scratch, total;
+};
+
+DetExtra det_extra(size_t base_total, int64_t n, int K, int C, const svlf_scene& sc) {
+  DetExtra d;
+  d.gxu = align256(base_total);
+  d.scratch = align256(d.gxu + static_cast<size_t>(n) * K * (C + 4) * sizeof(float));
+  d.total = align256(d.scratch + detgrad_bytes(n, K, C, sc.octree.n_leaves, sc.octree.n_vertices));
+  return d;
+}
+
 // Shared body of render / render_backward / train_step.
 int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_t* offs,
               const svlf_mlp* mlp, const svlf_render_opts* opts, const float* ray_o,
@@ -190,10 +205,18 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   if (n > 0 && (ray_o == nullptr || ray_d == nullptr))
     return fail(SVLF_E_INVAL, who_str(who, "ray_o / ray_d is NULL"));
   const WsLayout w = ws_layout(n, opts->K, sh.n_params);
-  if (ws == nullptr || ws_bytes < w.total)
-    return fail(SVLF_E_WORKSPACE, who_str(who, "workspace missing or smaller than svlf_workspace_bytes()"));
+  const bool det = (opts->flags & SVLF_FLAG_DETERMINISTIC) != 0 && mode != kForward;
+  if (det && n_scenes != 1)
+    return fail(SVLF_E_UNSUPPORTED, who_str(who, "SVLF_FLAG_DETERMINISTIC supports one scene"));
+  if (det && n * opts->K >= (int64_t(1) << 31))
+    return fail(SVLF_E_RANGE, who_str(who, "too many hit slots for SVLF_FLAG_DETERMINISTIC"));
+  const DetExtra dx = det ? det_extra(w.total, n, opts->K, sh.C, scenes[0]) : DetExtra{0, 0, w.total};
+  if (ws == nullptr || ws_bytes < dx.total)
+    return fail(SVLF_E_WORKSPACE, who_str(who, det ? "workspace smaller than svlf_workspace_bytes_scenes()"
+                                                   : "workspace missing or smaller than svlf_workspace_bytes()"));
   if (n == 0) return SVLF_OK;
   char* base = static_cast<char*>(ws);
+  a.gxu = det ? reinterpret_cast<float*>(base + dx.gxu) : nullptr;
   a.o = ray_o;
   a.d = ray_d;
   a.hits = reinterpret_cast<HitRec*>(base + w.hits);
@@ -225,6 +248,11 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   if (mode != kForward) {
     e = launch_reduce_partials(a.ws_partials, grid, sh.n_params, a.grad_params, a.ws_loss,
                                mode == kTrain ? a.loss_out : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+  }
+  if (det) {
+    e = launch_detgrad(a.tab.s[0], a.hits, a.cnt, n, opts->K, sh.C, a.gxu, base + dx.scratch,
+                       scenes[0].octree.n_leaves, scenes[0].octree.n_vertices, s);
     if (e != hipSuccess) return hip_fail(e, who);
   }
   return SVLF_OK;
@@ -564,7 +592,26 @@ size_t svlf_workspace_bytes(const svlf_mlp* mlp, const svlf_render_opts* opts, i
     fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
     return 0;
   }
+  if (opts->flags & SVLF_FLAG_DETERMINISTIC) {
+    fail(SVLF_E_INVAL, who_str(who, "with SVLF_FLAG_DETERMINISTIC use svlf_workspace_bytes_scenes"));
+    return 0;
+  }
   return ws_layout(n_rays, opts->K, sh.n_params).total;
+}
+
+size_t svlf_workspace_bytes_scenes(const svlf_mlp* mlp, const svlf_render_opts* opts,
+                                   const svlf_scene* scenes, int32_t n_scenes, int64_t n_rays) {
+  const char* who = "svlf_workspace_bytes_scenes";
+  if (check_opts(opts, who)) return 0;
+  MlpShape sh;
+  if (check_mlp(mlp, (opts->flags & SVLF_FLAG_VIEWDIR) != 0, &sh, who)) return 0;
+  if (n_rays < 0 || scenes == nullptr || n_scenes < 1 || n_scenes > SVLF_MAX_SCENES) {
+    fail(SVLF_E_INVAL, who_str(who, "invalid scenes / n_rays"));
+    return 0;
+  }
+  const size_t base = ws_layout(n_rays, opts->K, sh.n_params).total;
+  if (!(opts->flags & SVLF_FLAG_DETERMINISTIC) || n_scenes != 1) return base;
+  return det_extra(base, n_rays, opts->K, sh.C, scenes[0]).total;
 }
 
 int svlf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,

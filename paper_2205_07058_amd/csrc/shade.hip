@@ -739,10 +739,22 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
               const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
                           wz[2] = {1.0f - rc.uz, rc.uz};
               const float gv = gxs[hh * CF::C + c];
+              if (a.gxu != nullptr) {
+                // deterministic mode: keep (u, dL/dx) per hit slot; the
+                // feature gradient is reduced afterwards in a fixed order
+                const int mp = sm.hmap()[hh];
+                const int64_t slot =
+                    (sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads + (mp & 0xFFFF)) * a.K +
+                    (mp >> 16);
+                float* rec_out = a.gxu + slot * (CF::C + 4);
+                rec_out[4 + c] = gv;
+                if (c < 3) rec_out[c] = c == 0 ? rc.ux : (c == 1 ? rc.uy : rc.uz);
+              } else {
 #pragma unroll
-              for (int j = 0; j < 8; ++j) {
-                const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
-                unsafeAtomicAdd(sc.grad + static_cast<int64_t>(vid[j]) * CF::C + c, wj * gv);
+                for (int j = 0; j < 8; ++j) {
+                  const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
+                  unsafeAtomicAdd(sc.grad + static_cast<int64_t>(vid[j]) * CF::C + c, wj * gv);
+                }
               }
             }
           }

@@ -87,7 +87,16 @@ struct ShadeArgs {
   float* ws_partials;     // [grid][n_params] per-block dW partial sums
   float* ws_loss;         // [grid] per-block loss partial sums
   int64_t n_params;
+  float* gxu;             // deterministic mode: [n][K][C + 4] (u, dL/dx) per hit, else null
 };
+
+// Deterministic feature-gradient reduction (detgrad.hip): bucket the hit
+// slots by leaf, order each bucket by slot, and sum per vertex over its
+// (up to 8) adjacent leaves in a fixed order.
+size_t detgrad_bytes(int64_t n_rays, int K, int C, int64_t n_leaves, int64_t n_vertices);
+hipError_t launch_detgrad(const DevScene& sc, const HitRec* hits, const int32_t* cnt,
+                          int64_t n_rays, int K, int C, const float* gxu, void* scratch,
+                          int64_t n_leaves, int64_t n_vertices, hipStream_t s);
 
 enum ShadeMode { kForward = 0, kBackward = 1, kTrain = 2 };
 

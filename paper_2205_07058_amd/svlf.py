@@ -30,6 +30,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1}
 FLAG_TRACE_ONLY = 1
 FLAG_REUSE_HITS = 2
 FLAG_VIEWDIR = 4
+FLAG_DETERMINISTIC = 8
 
 
 class Node(ct.Structure):
@@ -132,6 +133,8 @@ _SIGS = {
     "svlf_occupancy_from_depth": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
                                    ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p],
                                   ct.c_int),
+    "svlf_workspace_bytes_scenes": ([ct.POINTER(Mlp), ct.POINTER(RenderOpts), ct.POINTER(Scene),
+                                     ct.c_int32, ct.c_int64], ct.c_size_t),
     "svlf_to_bf16": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_fill": ([ct.c_void_p, ct.c_float, ct.c_int64, ct.c_void_p], ct.c_int),
     "svlf_mlp_forward": ([ct.POINTER(Mlp), ct.POINTER(RenderOpts), ct.c_void_p, ct.c_int64,
@@ -373,11 +376,17 @@ def _scene_array(scenes, ray_counts):
     return arr, offs_c, int(offs[-1])
 
 
-def workspace_bytes(params, widths, opts: RenderOpts, n_rays) -> int:
+def workspace_bytes(params, widths, opts: RenderOpts, n_rays, scene_array=None, n_scenes=1) -> int:
     m = make_mlp(params, widths)
-    nb = load().svlf_workspace_bytes(ct.byref(m), ct.byref(opts), int(n_rays))
+    if opts.flags & FLAG_DETERMINISTIC:
+        nb = load().svlf_workspace_bytes_scenes(ct.byref(m), ct.byref(opts), scene_array, n_scenes,
+                                                int(n_rays))
+        name = "svlf_workspace_bytes_scenes"
+    else:
+        nb = load().svlf_workspace_bytes(ct.byref(m), ct.byref(opts), int(n_rays))
+        name = "svlf_workspace_bytes"
     if nb == 0:
-        raise SvlfError("svlf_workspace_bytes", E_INVAL, last_error())
+        raise SvlfError(name, E_INVAL, last_error())
     return nb
 
 
@@ -408,7 +417,7 @@ def render(scenes, ray_counts, params, widths, opts: RenderOpts, ray_o, ray_d, o
     if out_acc is None:
         out_acc = torch.empty((n,), dtype=torch.float32, device=dev)
     m = make_mlp(params, widths)
-    nb = workspace_bytes(params, widths, opts, n)
+    nb = workspace_bytes(params, widths, opts, n, arr, len(scenes))
     ws = (workspace or _default_ws).get(nb, dev)
     _check("svlf_render",
            load().svlf_render(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),
@@ -432,7 +441,7 @@ def render_backward(scenes, ray_counts, params, widths, opts: RenderOpts, ray_o,
     scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
     arr, offs, n = _scene_array(scenes, ray_counts)
     m = make_mlp(params, widths)
-    nb = workspace_bytes(params, widths, opts, n)
+    nb = workspace_bytes(params, widths, opts, n, arr, len(scenes))
     ws = (workspace or _default_ws).get(nb, ray_o.device)
     for g, s in zip(grad_features, scenes):
         _ptr(g, torch.float32, tuple(s.features.shape), "grad_features")
@@ -455,7 +464,7 @@ def train_step(scenes, ray_counts, params, widths, opts: RenderOpts, ray_o, ray_
     scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
     arr, offs, n = _scene_array(scenes, ray_counts)
     m = make_mlp(params, widths)
-    nb = workspace_bytes(params, widths, opts, n)
+    nb = workspace_bytes(params, widths, opts, n, arr, len(scenes))
     ws = (workspace or _default_ws).get(nb, ray_o.device)
     for g, s in zip(grad_features, scenes):
         _ptr(g, torch.float32, tuple(s.features.shape), "grad_features")

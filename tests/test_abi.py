@@ -88,7 +88,7 @@ def test_render_validation(lib):
     assert args(sc, 17, offs, ct.byref(m), ct.byref(opts), None, 0) == svlf.E_RANGE
     bad = svlf.make_opts(0)
     assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_RANGE
-    bad = svlf.make_opts(4, flags=8)
+    bad = svlf.make_opts(4, flags=16)
     assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_INVAL
     bad = svlf.make_opts(4, flags=svlf.FLAG_TRACE_ONLY | svlf.FLAG_REUSE_HITS)
     assert args(sc, 1, offs, ct.byref(m), ct.byref(bad), None, 0) == svlf.E_INVAL
@@ -250,3 +250,21 @@ def test_occupancy_validation(lib):
     p = ct.c_void_p(0x100)
     need = lib.svlf_occupancy_workspace_bytes(5)
     assert f(p, p, p, 10, 5, p, cnt, p, need - 1, None) == svlf.E_WORKSPACE
+
+
+def test_deterministic_workspace_query(lib):
+    """With SVLF_FLAG_DETERMINISTIC the scene-less workspace query refuses
+    and the scene-aware one adds the reduction's space."""
+    m = _mlp()
+    opts = svlf.make_opts(8, flags=svlf.FLAG_DETERMINISTIC)
+    assert lib.svlf_workspace_bytes(ct.byref(m), ct.byref(opts), 100) == 0
+    assert "svlf_workspace_bytes_scenes" in svlf.last_error()
+    sc = (svlf.Scene * 1)()
+    sc[0].octree.depth = 4
+    sc[0].octree.n_leaves = 1000
+    sc[0].octree.n_vertices = 3000
+    plain = svlf.make_opts(8)
+    base = lib.svlf_workspace_bytes_scenes(ct.byref(m), ct.byref(plain), sc, 1, 100)
+    assert base == lib.svlf_workspace_bytes(ct.byref(m), ct.byref(plain), 100)
+    det = lib.svlf_workspace_bytes_scenes(ct.byref(m), ct.byref(opts), sc, 1, 100)
+    assert det >= base + 100 * 8 * (8 + 4) * 4 + 3000 * 32

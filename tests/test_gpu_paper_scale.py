@@ -142,3 +142,30 @@ def test_lightfield_train_step_full_batch(gpu_lib, paper):
     g = gpu_lib.lf_feature_rows(gF.cpu().numpy(), sc.n_vertices)
     assert np.all(np.isfinite(g)) and np.abs(g[:, :64]).max() > 0 and np.abs(g[:, 64:]).max() > 0
     assert np.all(np.isfinite(gp.cpu().numpy()))
+
+
+def test_deterministic_train_step_paper_scale(gpu_lib, paper):
+    """Full 2^20-ray BF16 train step with the deterministic feature-gradient
+    reduction: two runs give bit-identical feature gradients, within FP32
+    accumulation tolerance of the atomic path."""
+    import torch
+    w = paper["w"]
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
+    n = ob.shape[0]
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    args = [T(ob), T(db), T(rgb_t), T(dep_t)]
+
+    def run(flags):
+        gF = torch.zeros_like(paper["scene"].features)
+        gp = torch.zeros_like(paper["params"])
+        gpu_lib.train_step([paper["scene"]], [n], paper["params"], w.widths,
+                           gpu_lib.make_opts(w.K, "voxel", "bf16", flags), *args, 0.1, 1.0 / n, [gF], gp)
+        torch.cuda.synchronize()
+        return gF.cpu().numpy()
+
+    a = run(gpu_lib.FLAG_DETERMINISTIC)
+    b = run(gpu_lib.FLAG_DETERMINISTIC)
+    assert np.array_equal(a.view(np.int32), b.view(np.int32))
+    c = run(0)
+    scale = np.abs(c).max()
+    assert scale > 0 and np.abs(a - c).max() <= 1e-5 * scale

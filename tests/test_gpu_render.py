@@ -257,3 +257,39 @@ def test_multi_scene_render_and_backward(gpu_lib):
         ep_total = ep_total + ep
         start += n
     assert_grad_close(gp.cpu().numpy(), ep_total, "multi grad_params", rel_nw=1e-4, rel_el=None)
+
+
+def test_deterministic_feature_gradient(gpu_lib):
+    """SVLF_FLAG_DETERMINISTIC: bit-identical feature gradients over repeated
+    calls, equal to the atomic path within the FP32 tolerance, and to the
+    oracle on kink-free rays; decoder gradients unchanged."""
+    import torch
+    for name, case in list(_scene_cases(gpu_lib))[:3]:
+        rng = np.random.default_rng(41)
+        o, d = random_rays(rng, 3000, inside_frac=0.2)
+        keep = case.smooth_rays(o, d)
+        o, d = o[keep], d[keep]
+        n = o.shape[0]
+        g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+        g_dep = rng.normal(size=n).astype(np.float32)
+        to, td = case.rays(o, d)
+        t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+
+        def run(flags):
+            gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+            gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+            opts = gpu_lib.make_opts(case.K, case.tau_mode, "fp32", flags)
+            gpu_lib.render_backward([case.scene], [n], case.params, case.widths, opts, to, td,
+                                    t(g_rgb), t(g_dep), None, [gF], gp)
+            torch.cuda.synchronize()
+            return gF.cpu().numpy(), gp.cpu().numpy()
+
+        gF1, gp1 = run(gpu_lib.FLAG_DETERMINISTIC)
+        gF2, _ = run(gpu_lib.FLAG_DETERMINISTIC)
+        assert np.array_equal(gF1.view(np.int32), gF2.view(np.int32)), name
+        gFa, gpa = run(0)
+        _, _, _, st = case.oracle(o, d)
+        eF, ep = render_backward(st, g_rgb, g_dep)
+        assert_grad_close(gF1, eF, f"{name} deterministic grad_features")
+        assert_grad_close(gF1, gFa, f"{name} deterministic vs atomic")
+        np.testing.assert_array_equal(gp1, gpa)
