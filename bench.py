@@ -99,7 +99,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=4096,
+    ap.add_argument("--cpu-rays", type=int, default=1 << 17,
                     help="rays of the batch the oracle trains on for the CPU baseline")
     ap.add_argument("--psnr-rays", type=int, default=16384)
     ap.add_argument("--sections", default="all",
