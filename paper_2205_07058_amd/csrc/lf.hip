@@ -352,6 +352,7 @@ __device__ __forceinline__ void dw_window(const typename Types<BF>::El* GZ,
       } else {
         acc = mma(ga_[2 * s + g], gb_[2 * s + g], acc);
       }
+      chunk_fence<BF ? 2 : 8>(s);
     }
     const int col = 32 * nt + (lane & 31);
 #pragma unroll
@@ -704,25 +705,35 @@ struct CCfg {
   using M = typename Dec<BF, VD>::C;
   using El = typename Types<BF>::Elem;
   static constexpr int EB = Types<BF>::EB;
-  static constexpr int WIN = BWD ? (BF ? 64 : 32) : (BF ? 128 : 64);
+  // BF16 backward keeps the activations of hidden layers 1 and 2 in
+  // registers (packed) and those of layer 0 transposed in LDS, staging one
+  // register layer at a time for the weight gradients; this allows 128-hit
+  // windows (all four waves own a tile).  FP32 keeps all three layers
+  // transposed in LDS at 32-hit windows.
+  static constexpr bool ACT_REG = BF;
+  static constexpr int L0_ROW = ACT_REG ? kLfH : 0;     // LDS row of layer 0's activations
+  static constexpr int WIN = BWD ? (BF ? 128 : 32) : (BF ? 128 : 64);
   static constexpr int NTILE = WIN / 32;
   static constexpr int XS = M::IN0P + (BF ? 8 : 4);
   static constexpr int TS = WIN + (BF ? 8 : 1);
   static constexpr int XT_ROWS = align32(M::IN0);
   static constexpr int NB_PER_T = (M::NBIAS + kThreads - 1) / kThreads;
-  // LDS: records, X, per-hit out (8 floats), then (backward) hidden
-  // activations [NH][H][TS], X^T [XT_ROWS][TS] and GZ [H][TS]
+  // LDS: records, X, per-hit out (8 floats), then (backward) the hidden
+  // activations [NH][H][TS] (or, with ACT_REG, one staged layer [H][TS] that
+  // also takes X^T), X^T [XT_ROWS][TS] and GZ [H][TS]
+  static constexpr int ACT_ROWS = ACT_REG ? 2 * kLfH : kLfNHC * kLfH;
   static constexpr int L_REC = 0;
   static constexpr int L_X = L_REC + WIN * 64;
   static constexpr int L_OUT = align16(L_X + WIN * XS * EB);
   static constexpr int L_ACT = align16(L_OUT + WIN * 32);
-  static constexpr int L_XT = align16(L_ACT + (BWD ? kLfNHC * kLfH * TS * EB : 0));
-  static constexpr int L_GZ = align16(L_XT + (BWD ? XT_ROWS * TS * EB : 0));
+  static constexpr int L_XT = align16(L_ACT + (BWD ? ACT_ROWS * TS * EB : 0));
+  static constexpr int L_GZ = align16(L_XT + ((BWD && !ACT_REG) ? XT_ROWS * TS * EB : 0));
   static constexpr int L_MAP = align16(L_GZ + (BWD ? kLfH * TS * EB : 0));
   static constexpr int L_SCR = align16(L_MAP + WIN * 4);
   static constexpr int LDS = L_SCR + 64;
   static_assert(LDS <= 160 * 1024, "LDS");
   static_assert(!BWD || WIN * kLfCC * 4 <= kLfH * TS * EB, "dL/dz_C staging fits in GZ");
+  static_assert(XT_ROWS <= kLfH, "X^T fits in the staged-activation area");
 };
 
 // Colour record (64 B): unclamped surface point in cell units, t_in, t_out,
@@ -872,6 +883,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
       const int n0 = 32 * wave;
       const bool has_tile = wave < CF::NTILE && n0 < tw;
       const int col = n0 + (lane & 31);
+      ActT<BF> act[CF::ACT_REG && CF::BWD ? M::NH - 1 : 1][M::MTH];   // layers 1 .. NH-1
       if (has_tile) {
         const int row = col;
         f32x16 cur[M::MTH];
@@ -894,7 +906,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
 #pragma unroll
             for (int mt = 0; mt < M::MTH; ++mt)
 #pragma unroll
-              for (int i = 0; i < 16; ++i) cACT<CF>()[(32 * mt + drow(i, g)) * CF::TS + col] = to_el<BF>(cur[mt][i]);
+              for (int i = 0; i < 16; ++i)
+                cACT<CF>()[(CF::L0_ROW + 32 * mt + drow(i, g)) * CF::TS + col] = to_el<BF>(cur[mt][i]);
           }
         }
         static_for<M::NH - 1>([&](auto lc) {
@@ -915,7 +928,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
             relu16(nxt[mt]);
             cur[mt] = nxt[mt];
           }
-          if constexpr (CF::BWD) {
+          if constexpr (CF::BWD && CF::ACT_REG) {
+#pragma unroll
+            for (int mt = 0; mt < M::MTH; ++mt) act[l - 1][mt].set(cur[mt]);
+          } else if constexpr (CF::BWD) {
 #pragma unroll
             for (int mt = 0; mt < M::MTH; ++mt)
 #pragma unroll
@@ -934,7 +950,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
           *reinterpret_cast<f32x4*>(out + 8 * col) = f32x4{sigmoidf_(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), 0.0f};
       } else if (CF::BWD && wave < CF::NTILE) {
         // no hits for this tile: its activation columns must not hold stale data
-        for (int rr = g; rr < kLfNHC * kLfH; rr += 2) cACT<CF>()[rr * CF::TS + col] = to_el<BF>(0.0f);
+        constexpr int R0 = CF::ACT_REG ? CF::L0_ROW : 0;
+        constexpr int R1 = CF::ACT_REG ? CF::L0_ROW + kLfH : kLfNHC * kLfH;
+        for (int rr = R0 + g; rr < R1; rr += 2) cACT<CF>()[rr * CF::TS + col] = to_el<BF>(0.0f);
       }
       __syncthreads();
 
@@ -1068,18 +1086,30 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
               for (int mt = 0; mt < OT; ++mt)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) GZ[(32 * mt + drow(i, g)) * CF::TS + col] = to_el<BF>(gz[mt][i]);
+              if constexpr (CF::ACT_REG && l > 1) {
+#pragma unroll
+                for (int mt = 0; mt < M::MTH; ++mt)
+#pragma unroll
+                  for (int i = 0; i < 16; ++i) cACT<CF>()[(32 * mt + drow(i, g)) * CF::TS + col] = act[l - 2][mt].elem(i);
+              }
             } else {
               for (int rr = g; rr < 32 * OT; rr += 2) GZ[rr * CF::TS + col] = to_el<BF>(0.0f);
+              if constexpr (CF::ACT_REG && l > 1)
+                for (int rr = g; rr < kLfH; rr += 2) cACT<CF>()[rr * CF::TS + col] = to_el<BF>(0.0f);
             }
           }
+          El* XTs = CF::ACT_REG ? cACT<CF>() : XT;      // X^T (layer 0)
           if constexpr (l == 0) {
             for (int e = tid; e < CF::WIN * CF::XT_ROWS; e += kThreads) {
               const int hh = e % CF::WIN, c = e / CF::WIN;
-              XT[c * CF::TS + hh] = c < M::IN0P ? cX<CF>()[hh * CF::XS + c] : to_el<BF>(0.0f);
+              XTs[c * CF::TS + hh] = c < M::IN0P ? cX<CF>()[hh * CF::XS + c] : to_el<BF>(0.0f);
             }
           }
           __syncthreads();
-          const El* AT = (l == 0) ? XT : cACT<CF>() + (l - 1) * kLfH * CF::TS;
+          // layer l's input: X^T (l = 0), layer 0 from LDS, or the staged register layer
+          const El* AT = (l == 0) ? XTs
+                         : CF::ACT_REG ? cACT<CF>() + (l == 1 ? CF::L0_ROW * CF::TS : 0)
+                                       : cACT<CF>() + (l - 1) * kLfH * CF::TS;
           if (!a.freeze_color) dw_window<BF, M, l, CF::WIN, CF::TS>(GZ, AT, part, wave, lane);
 #pragma unroll
           for (int bi = 0; bi < CF::NB_PER_T; ++bi) {
@@ -1110,13 +1140,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
               for (int mt = 0; mt < BMT; ++mt) rr_[mt] = mma(gopb<BF>(rs, BB, mt, s, S, lane), bo, rr_[mt]);
               chunk_fence<kChunk<BF>>(s);
             }
-            if constexpr (l > 0) {
-              const El* act = cACT<CF>() + (l - 1) * kLfH * CF::TS;
+            if constexpr (l > 1 && CF::ACT_REG) {
+#pragma unroll
+              for (int mt = 0; mt < M::MTH; ++mt)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) gz[mt][i] = act[l - 2][mt].positive(i) ? rr_[mt][i] : 0.0f;
+            } else if constexpr (l > 0) {
+              const El* actl = cACT<CF>() + (CF::ACT_REG ? CF::L0_ROW : (l - 1) * kLfH) * CF::TS;
 #pragma unroll
               for (int mt = 0; mt < M::MTH; ++mt)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                  const El av = act[(32 * mt + drow(i, g)) * CF::TS + col];
+                  const El av = actl[(32 * mt + drow(i, g)) * CF::TS + col];
                   bool pos;
                   if constexpr (BF) pos = static_cast<short>(av) > 0;
                   else pos = av > 0.0f;
