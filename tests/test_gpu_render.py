@@ -293,3 +293,44 @@ def test_deterministic_feature_gradient(gpu_lib):
         assert_grad_close(gF1, eF, f"{name} deterministic grad_features")
         assert_grad_close(gF1, gFa, f"{name} deterministic vs atomic")
         np.testing.assert_array_equal(gp1, gpa)
+
+
+def test_max_K_solid_scene(gpu_lib):
+    """K = 16 (the largest hit cap) on a solid scene where many rays have 16
+    hits: windows hold few rays each; forward and backward against the
+    oracle, and the light-field path on the same scene."""
+    from tests.gpu_cases import LfCase
+    from oracle.lightfield import render_lf_backward
+    w = tiny_workload(17, 5, 16, (16, 64, 64, 64, 4), 16, n_obj=3)
+    case = Case.from_workload(gpu_lib, w, feat_scale=3.0, sigma_bias=0.3)
+    rng = np.random.default_rng(5)
+    o, d = random_rays(rng, 2500, inside_frac=0.3)
+    rgb, dep, acc = case.gpu_render(o, d)
+    er, ed, ea, st = case.oracle(o, d)
+    counts = np.bincount(st.ray_i, minlength=o.shape[0])
+    assert counts.max() == 16 and np.mean(counts == 16) > 0.05
+    assert_outputs_close(rgb, er, 1.0, "K16 rgb")
+    assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), "K16 depth")
+    keep = case.smooth_rays(o, d)
+    g_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)
+    g_dep = rng.normal(size=keep.size).astype(np.float32)
+    gF, gp = _gpu_backward(case, o[keep], d[keep], g_rgb, g_dep, None)
+    _, _, _, st2 = case.oracle(o[keep], d[keep])
+    eF, ep = render_backward(st2, g_rgb, g_dep)
+    assert_grad_close(gF, eF, "K16 grad_features")
+    assert_grad_close(gp, ep, "K16 grad_params", rel_nw=1e-4, rel_el=None)
+    lf = LfCase(gpu_lib, w.scene().leaf_ijk, 5,
+                np.random.default_rng(1).normal(0, 0.5, (w.scene().n_vertices, 96)).astype(np.float32),
+                LfCase.random(gpu_lib, 17, 5, K=16).p, 16)
+    lrgb, ldep, lacc = lf.gpu_render(o, d)
+    lr, ld, la, lst = lf.oracle(o, d)
+    assert_outputs_close(lrgb, lr, 1.0, "K16 lf rgb")
+    assert_outputs_close(ldep, ld, max(1.0, np.abs(ld).max()), "K16 lf depth")
+    keep = lf.smooth_rays(o, d)
+    lg_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)
+    lg_dep = rng.normal(size=keep.size).astype(np.float32)
+    lgF, lgp = lf.gpu_backward(o[keep], d[keep], lg_rgb, lg_dep)
+    _, _, _, lst2 = lf.oracle(o[keep], d[keep])
+    leF, lep = render_lf_backward(lst2, lg_rgb, lg_dep)
+    assert_grad_close(lgF, leF, "K16 lf grad_features")
+    assert_grad_close(lgp, lep, "K16 lf grad_params", rel_nw=1e-4, rel_el=None)
