@@ -337,9 +337,18 @@ typedef struct {
  * or 0 with the error set if the model is unsupported. */
 int64_t svlf_lf_param_count(const svlf_lf_model* model, const svlf_render_opts* opts);
 
-/* Workspace bytes for n_rays rays (0 on invalid arguments). */
+/* Workspace bytes for n_rays rays, enough for every light-field call (0 on
+ * invalid arguments).  With BF16 precision, calls that run a backward pass
+ * (svlf_lf_render_backward, svlf_lf_train_step, svlf_lf_train_stage) keep
+ * the density decoder's input row of every hit slot in it (n_rays * K * 288
+ * bytes) instead of gathering the features a second time. */
 size_t svlf_lf_workspace_bytes(const svlf_lf_model* model, const svlf_render_opts* opts,
                                int64_t n_rays);
+
+/* Workspace bytes sufficient for svlf_lf_render alone (forward only); never
+ * larger than svlf_lf_workspace_bytes. */
+size_t svlf_lf_render_workspace_bytes(const svlf_lf_model* model, const svlf_render_opts* opts,
+                                      int64_t n_rays);
 
 /* Forward render with the light-field function; arguments as svlf_render. */
 int svlf_lf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,

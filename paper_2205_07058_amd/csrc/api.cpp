@@ -280,12 +280,13 @@ int check_lf_model(const svlf_lf_model* m, const svlf_render_opts* opts, int64_t
 }
 
 // Workspace: [hit slots][counts][per-hit state][dL/d(o_T0, o_T1)][decoder
-// packs][per-block partials of F_T][of F_C][per-block loss]
+// packs][per-block partials of F_T][of F_C][per-block loss][BF16 calls with
+// a backward pass: the density decoder's input rows per hit slot]
 struct LfLayout {
-  size_t hits, cnt, st, gT, packs, partT, partC, loss, total;
+  size_t hits, cnt, st, gT, packs, partT, partC, loss, xs, total;
 };
 
-LfLayout lf_layout(int64_t n, int K, int precision, int viewdir) {
+LfLayout lf_layout(int64_t n, int K, int precision, int viewdir, bool backward) {
   LfLayout w;
   const size_t slots = static_cast<size_t>(n) * K;
   const size_t grid = static_cast<size_t>(lf_grid_limit());
@@ -306,6 +307,9 @@ LfLayout lf_layout(int64_t n, int K, int precision, int viewdir) {
   off = align256(off + grid * lf_params_color(viewdir) * sizeof(float));
   w.loss = off;
   off = align256(off + grid * sizeof(float));
+  w.xs = off;
+  if (backward && precision == SVLF_BF16)
+    off = align256(off + slots * static_cast<size_t>(lf_x_row()) * sizeof(uint16_t));
   w.total = off;
   return w;
 }
@@ -327,9 +331,11 @@ int run_lf_call(int mode, const svlf_scene* scenes, int32_t n_scenes, const int6
   if (n > 0 && (ray_o == nullptr || ray_d == nullptr))
     return fail(SVLF_E_INVAL, who_str(who, "ray_o / ray_d is NULL"));
   const int vd = (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0;
-  const LfLayout w = lf_layout(n, opts->K, opts->precision, vd);
+  const LfLayout w = lf_layout(n, opts->K, opts->precision, vd, need_grads);
   if (ws == nullptr || ws_bytes < w.total)
-    return fail(SVLF_E_WORKSPACE, who_str(who, "workspace missing or smaller than svlf_lf_workspace_bytes()"));
+    return fail(SVLF_E_WORKSPACE,
+                who_str(who, need_grads ? "workspace missing or smaller than svlf_lf_workspace_bytes()"
+                                        : "workspace missing or smaller than svlf_lf_render_workspace_bytes()"));
   if (n == 0) return SVLF_OK;
   char* base = static_cast<char*>(ws);
   a.o = ray_o;
@@ -342,6 +348,8 @@ int run_lf_call(int mode, const svlf_scene* scenes, int32_t n_scenes, const int6
   a.partT = reinterpret_cast<float*>(base + w.partT);
   a.partC = reinterpret_cast<float*>(base + w.partC);
   a.ws_loss = reinterpret_cast<float*>(base + w.loss);
+  a.xsave = (need_grads && opts->precision == SVLF_BF16) ? reinterpret_cast<uint16_t*>(base + w.xs)
+                                                         : nullptr;
   a.K = opts->K;
   a.tau_mode = opts->tau_mode;
   a.precision = opts->precision;
@@ -381,7 +389,21 @@ size_t svlf_lf_workspace_bytes(const svlf_lf_model* model, const svlf_render_opt
     fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
     return 0;
   }
-  return lf_layout(n_rays, opts->K, opts->precision, (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0).total;
+  return lf_layout(n_rays, opts->K, opts->precision, (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0, true)
+      .total;
+}
+
+size_t svlf_lf_render_workspace_bytes(const svlf_lf_model* model, const svlf_render_opts* opts,
+                                      int64_t n_rays) {
+  const char* who = "svlf_lf_render_workspace_bytes";
+  if (check_opts(opts, who)) return 0;
+  if (svlf_lf_param_count(model, opts) == 0) return 0;
+  if (n_rays < 0) {
+    fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
+    return 0;
+  }
+  return lf_layout(n_rays, opts->K, opts->precision, (opts->flags & SVLF_FLAG_VIEWDIR) ? 1 : 0, false)
+      .total;
 }
 
 int svlf_lf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_offsets_host,

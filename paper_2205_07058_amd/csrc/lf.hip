@@ -444,6 +444,46 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
       const int s1 = open_window<CF::WIN>(s0, total, off, count, scr, hmap, in_win);
       const int tw = s1 - s0;
       (void)in_win;
+      if (BF && CF::BWD && a.xsave != nullptr) {
+        // the forward pass saved this window's decoder inputs: one thread per
+        // hit rebuilds its record, the rows stream back 16 B per thread
+        for (int hh = tid; hh < CF::WIN; hh += kThreads) {
+          if (hh < tw) {
+            const int mp = hmap[hh];
+            const int64_t ray = ray0 + (mp & 0xFFFF);
+            const HitRec hr = a.hits[ray * a.K + (mp >> 16)];
+            const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
+            const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
+            const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hr.leaf));
+            const float lx = -1.0f + static_cast<float>(hr.ijk & 1023u) * h;
+            const float ly = -1.0f + static_cast<float>((hr.ijk >> 10) & 1023u) * h;
+            const float lz = -1.0f + static_cast<float>(hr.ijk >> 20) * h;
+            DRec rc;
+            rc.u1[0] = (fmaf(hr.tin, dx, ox) - lx) * inv_h;
+            rc.u1[1] = (fmaf(hr.tin, dy, oy) - ly) * inv_h;
+            rc.u1[2] = (fmaf(hr.tin, dz, oz) - lz) * inv_h;
+            rc.u2[0] = (fmaf(hr.tout, dx, ox) - lx) * inv_h;
+            rc.u2[1] = (fmaf(hr.tout, dy, oy) - ly) * inv_h;
+            rc.u2[2] = (fmaf(hr.tout, dz, oz) - lz) * inv_h;
+            rc.tin = hr.tin;
+            rc.tout = hr.tout;
+            rc.v0 = lc[0];
+            rc.v1 = lc[1];
+            rec[hh] = rc;
+          }
+        }
+        constexpr int CPR = M::IN0P * 2 / 16;   // 16-byte chunks per row
+        for (int e = tid; e < CF::WIN * CPR; e += kThreads) {
+          const int hh = e / CPR, c = e % CPR;
+          uint4 v = make_uint4(0u, 0u, 0u, 0u);
+          if (hh < tw) {
+            const int mp = hmap[hh];
+            const int64_t slot = (ray0 + (mp & 0xFFFF)) * a.K + (mp >> 16);
+            v = *reinterpret_cast<const uint4*>(a.xsave + slot * M::IN0P + 8 * c);
+          }
+          *reinterpret_cast<uint4*>(dX<CF>() + hh * CF::XS + 8 * c) = v;
+        }
+      } else {
       // gather: thread q of a hit owns VPT channels of psi(x1) and psi(x2)
       {
         constexpr int TPH = kLfCT * CF::EB / 16;
@@ -520,7 +560,19 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           }
         }
       }
+      }
       __syncthreads();
+      if (BF && !CF::BWD && a.xsave != nullptr) {
+        // save the window's decoder inputs for the backward pass
+        constexpr int CPR = M::IN0P * 2 / 16;
+        for (int e = tid; e < tw * CPR; e += kThreads) {
+          const int hh = e / CPR, c = e % CPR;
+          const int mp = hmap[hh];
+          const int64_t slot = (ray0 + (mp & 0xFFFF)) * a.K + (mp >> 16);
+          *reinterpret_cast<uint4*>(a.xsave + slot * M::IN0P + 8 * c) =
+              *reinterpret_cast<const uint4*>(dX<CF>() + hh * CF::XS + 8 * c);
+        }
+      }
 
       const int n0 = 32 * wave;
       const bool has_tile = wave < CF::NTILE && n0 < tw;
@@ -1354,6 +1406,7 @@ hipError_t run_lf(const LfArgs& a, int mode, hipStream_t s) {
 }  // namespace
 
 int lf_grid_limit() { return 256; }
+int lf_x_row() { return Dec<true, 0>::T::IN0P; }
 int64_t lf_params_density() { return Dec<true, 0>::T::NPARAMS; }
 int64_t lf_params_color(int viewdir) {
   return viewdir ? Dec<true, 1>::C::NPARAMS : Dec<true, 0>::C::NPARAMS;

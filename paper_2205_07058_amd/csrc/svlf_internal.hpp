@@ -125,6 +125,7 @@ int lf_grid_limit();      // blocks of each light-field kernel (workspace partia
 int64_t lf_params_density();
 int64_t lf_params_color(int viewdir);
 size_t lf_pack_bytes(int precision, int viewdir);   // both decoders' MFMA packs
+int lf_x_row();           // BF16 elements of one saved density-decoder input row
 
 struct LfArgs {
   SceneTable tab;
@@ -139,6 +140,8 @@ struct LfArgs {
   const float* params;    // FP32 masters: density layers then colour layers
   LfHit* st;              // [n][K]
   float* gT;              // [n][K][2]: dL/d(o_T0, o_T1)
+  uint16_t* xsave;        // [n][K][lf_x_row()] BF16 density-decoder inputs written by
+                          // the forward density pass for the backward one (nullable)
   void* packs;            // lf_pack_bytes()
   float* rgb;
   float* depth;

@@ -112,6 +112,8 @@ _SIGS = {
                              ct.c_void_p, ct.c_int32, ct.c_void_p], ct.c_int),
     "svlf_lf_param_count": ([ct.POINTER(LfModel), ct.POINTER(RenderOpts)], ct.c_int64),
     "svlf_lf_workspace_bytes": ([ct.POINTER(LfModel), ct.POINTER(RenderOpts), ct.c_int64], ct.c_size_t),
+    "svlf_lf_render_workspace_bytes": ([ct.POINTER(LfModel), ct.POINTER(RenderOpts), ct.c_int64],
+                                       ct.c_size_t),
     "svlf_lf_render": ([ct.POINTER(Scene), ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(LfModel),
                         ct.POINTER(RenderOpts), ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                         ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p], ct.c_int),
@@ -567,6 +569,14 @@ def lf_workspace_bytes(opts: RenderOpts, n_rays) -> int:
     return nb
 
 
+def lf_render_workspace_bytes(opts: RenderOpts, n_rays) -> int:
+    m = make_lf_model()
+    nb = load().svlf_lf_render_workspace_bytes(ct.byref(m), ct.byref(opts), int(n_rays))
+    if nb == 0:
+        raise SvlfError("svlf_lf_render_workspace_bytes", E_INVAL, last_error())
+    return nb
+
+
 def _lf_params(params, opts):
     torch = _torch()
     return _ptr(params, torch.float32, (lf_param_count(opts),), "params").value
@@ -586,7 +596,7 @@ def lf_render(scenes, ray_counts, params, opts: RenderOpts, ray_o, ray_d, out_rg
         out_acc = torch.empty((n,), dtype=torch.float32, device=dev)
     m = make_lf_model()
     m.params = _lf_params(params, opts)
-    nb = lf_workspace_bytes(opts, n)
+    nb = lf_render_workspace_bytes(opts, n)
     ws = (workspace or _default_ws).get(nb, dev)
     _check("svlf_lf_render",
            load().svlf_lf_render(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),

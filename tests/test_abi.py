@@ -231,9 +231,24 @@ def test_lf_validation(lib):
     assert call(bad, None, 0) == svlf.E_UNSUPPORTED
     assert call(m, None, 0) == svlf.E_INVAL                     # params NULL
     m.params = 0x100
-    need = lib.svlf_lf_workspace_bytes(ct.byref(m), ct.byref(opts), 100)
-    assert need > 100 * 8 * (16 + 32 + 8)
-    assert call(m, ct.c_void_p(0x100), need - 1) == svlf.E_WORKSPACE
+    need_r = lib.svlf_lf_render_workspace_bytes(ct.byref(m), ct.byref(opts), 100)
+    assert need_r > 100 * 8 * (16 + 32 + 8)
+    assert call(m, ct.c_void_p(0x100), need_r - 1) == svlf.E_WORKSPACE
+    assert "svlf_lf_render_workspace_bytes" in svlf.last_error()
+    # FP32 calls need the same space in both modes; BF16 calls with a backward
+    # pass keep the density decoder's inputs per hit slot
+    assert need_r == lib.svlf_lf_workspace_bytes(ct.byref(m), ct.byref(opts), 100)
+    bopts = svlf.make_opts(8, precision="bf16")
+    need_rb = lib.svlf_lf_render_workspace_bytes(ct.byref(m), ct.byref(bopts), 100)
+    need = lib.svlf_lf_workspace_bytes(ct.byref(m), ct.byref(bopts), 100)
+    assert need >= need_rb + 100 * 8 * 288
+    gp = ct.c_void_p(0x100)
+    gf = ct.cast((ct.c_void_p * 1)(0x100), ct.c_void_p)
+    back = lambda wsb: lib.svlf_lf_render_backward(sc, 1, offs, ct.byref(m), ct.byref(bopts),
+                                                   gp, gp, gp, gp, None, gf, gp,
+                                                   ct.c_void_p(0x100), wsb, None)
+    assert back(need - 1) == svlf.E_WORKSPACE
+    assert "svlf_lf_workspace_bytes" in svlf.last_error()
 
 
 def test_occupancy_validation(lib):
