@@ -376,13 +376,12 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
   f32x16 dw[CF::DW_SLOTS > 0 ? CF::DW_SLOTS : 1];
 #pragma unroll
   for (int i = 0; i < CF::DW_SLOTS; ++i) dw[i] = zero16();
-  float db = 0.0f;
-  int db_layer = -1, db_row = 0;
-  if (CF::BWD && tid < CF::NBIAS) {
-    db_layer = tid / CF::H;
-    db_row = tid % CF::H;
-    if (db_layer > CF::NH) db_layer = CF::NH;
-  }
+  // bias gradients: for layer l, thread (row = tid % out_w, part = tid /
+  // out_w) sums its share of every window's hits; the parts are combined
+  // once at the end
+  float dbp[CF::NL];
+#pragma unroll
+  for (int l = 0; l < CF::NL; ++l) dbp[l] = 0.0f;
   float loss_acc = 0.0f;
 
   // Items (256-ray blocks) are dealt round-robin over the persistent grid
@@ -679,21 +678,27 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
               }
             });
           }
-          if (db_layer == l && db_row < out_real(l, CF::H, CF::NH)) {
-            const typename CF::Elem* gr_ = sm.GZ() + db_row * CF::TS;
-            float sacc = 0.0f;
-            if constexpr (CF::BF) {
-#pragma unroll 4
-              for (int hh = 0; hh < CF::WIN; hh += 8) {
-                const s16x8 v = *reinterpret_cast<const s16x8*>(gr_ + hh);
+          {
+            constexpr int RW = out_w(l, CF::H, CF::NH);
+            constexpr int HP = CF::WIN / (kThreads / RW);     // hits per part
+            static_assert(kThreads % RW == 0 && (!CF::BF || HP % 8 == 0), "bias-gradient parts");
+            const int row = tid % RW, pt = tid / RW;
+            if (row < out_real(l, CF::H, CF::NH)) {
+              const typename CF::Elem* gr_ = sm.GZ() + row * CF::TS + pt * HP;
+              float sacc = 0.0f;
+              if constexpr (CF::BF) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) sacc += bf16_f32(static_cast<uint16_t>(v[j]));
+                for (int hh = 0; hh < HP; hh += 8) {
+                  const s16x8 v = *reinterpret_cast<const s16x8*>(gr_ + hh);
+#pragma unroll
+                  for (int j = 0; j < 8; ++j) sacc += bf16_f32(static_cast<uint16_t>(v[j]));
+                }
+              } else {
+#pragma unroll
+                for (int hh = 0; hh < HP; ++hh) sacc += gr_[hh];
               }
-            } else {
-#pragma unroll 8
-              for (int hh = 0; hh < CF::WIN; ++hh) sacc += gr_[hh];
+              dbp[l] += sacc;
             }
-            db += sacc;
           }
           // data gradient to the layer input
           if (has_tile) {
@@ -804,16 +809,26 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         }
       });
     });
-    if (db_layer >= 0) {
-      const int orl = db_layer == CF::NH ? 4 : CF::H;
-      if (db_row < orl) {
-        int pb = 0;
-        static_for<CF::NL>([&](auto lc) {
-          constexpr int l = decltype(lc)::value;
-          if (l == db_layer) pb = par_b(l, CF::CIN, CF::H, CF::NH);
-        });
-        part[pb + db_row] = db;
-      }
+    // bias gradients: combine the parts through LDS ([layer][part][row])
+    static_assert(CF::NL * kThreads * 4 <= CF::TROWS * CF::TS * CF::EB, "bias parts fit in GZ");
+    float* bsc = reinterpret_cast<float*>(sm.GZ());
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < CF::NL; ++l) bsc[l * kThreads + tid] = dbp[l];
+    __syncthreads();
+    if (tid < CF::NBIAS) {
+      const int bl = tid / CF::H < CF::NH ? tid / CF::H : CF::NH;
+      const int br = tid - bl * CF::H;
+      static_for<CF::NL>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        constexpr int RW = out_w(l, CF::H, CF::NH);
+        if (l == bl) {
+          float sum = 0.0f;
+#pragma unroll
+          for (int pt = 0; pt < kThreads / RW; ++pt) sum += bsc[l * kThreads + pt * RW + br];
+          part[par_b(l, CF::CIN, CF::H, CF::NH) + br] = sum;
+        }
+      });
     }
     if (CF::MODE == kTrain) {
       const float tot = block_sum<kWaves>(loss_acc, reinterpret_cast<float*>(sm.scr()));
