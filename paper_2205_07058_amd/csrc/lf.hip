@@ -392,6 +392,53 @@ struct DCfg {
   static_assert(M::NBIAS <= kThreads, "bias gradients owned one per thread");
 };
 
+// Bias gradients of layer l (ROWS real rows of width RW in GZ, one column
+// per hit of the window): thread (row = tid % RW, part = tid / RW) adds its
+// slice of the window's hits to its own register; the parts are combined
+// once per block by bias_combine.
+template <bool BF, int RW, int ROWS, int WIN, int TS, class El>
+__device__ __forceinline__ void bias_part(const El* GZ, int tid, float& acc) {
+  constexpr int HP = WIN / (kThreads / RW);
+  static_assert(kThreads % RW == 0 && (!BF || HP % 8 == 0), "bias-gradient parts");
+  const int row = tid % RW, pt = tid / RW;
+  if (row >= ROWS) return;
+  const El* gr = GZ + row * TS + pt * HP;
+  float sum = 0.0f;
+  if constexpr (BF) {
+#pragma unroll
+    for (int hh = 0; hh < HP; hh += 8) {
+      const s16x8 v = *reinterpret_cast<const s16x8*>(gr + hh);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sum += bf16_f32(static_cast<uint16_t>(v[j]));
+    }
+  } else {
+#pragma unroll
+    for (int hh = 0; hh < HP; ++hh) sum += gr[hh];
+  }
+  acc += sum;
+}
+
+// Sums every layer's parts (through `lds`, NL * kThreads floats) into the
+// block's partial gradient.  Called by all threads.
+template <class M>
+__device__ __forceinline__ void bias_combine(const float (&acc)[M::NL], float* lds, float* part,
+                                             int tid) {
+  __syncthreads();
+#pragma unroll
+  for (int l = 0; l < M::NL; ++l) lds[l * kThreads + tid] = acc[l];
+  __syncthreads();
+  static_for<M::NL>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    constexpr int RW = M::out_p(l);
+    if (tid < M::out_r(l)) {
+      float sum = 0.0f;
+#pragma unroll
+      for (int pt = 0; pt < kThreads / RW; ++pt) sum += lds[l * kThreads + pt * RW + tid];
+      part[M::par_b(l) + tid] = sum;
+    }
+  });
+}
+
 // Density record (64 B): unclamped cell coordinates of x1 and x2, t_in,
 // t_out and the 8 corner ids.
 struct DRec {
@@ -424,9 +471,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
     for (int i = tid; i < M::NPARAMS; i += kThreads) part[i] = 0.0f;
     __syncthreads();
   }
-  float db = 0.0f;
-  const int db_layer = (CF::BWD && tid < M::NBIAS) ? (tid < kLfH ? 0 : 1) : -1;
-  const int db_row = tid < kLfH ? tid : tid - kLfH;
+  float dbp[M::NL];
+#pragma unroll
+  for (int l = 0; l < M::NL; ++l) dbp[l] = 0.0f;
 
   const int G = gridDim.x, bidx = blockIdx.x;
   const int lb = (G % 8 == 0) ? (bidx % 8) * (G / 8) + bidx / 8 : bidx;
@@ -675,15 +722,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           }
           __syncthreads();
           dw_window<BF, M, l, CF::WIN, CF::TS>(GZ, AT, part, wave, lane);
-          if (db_layer == l && db_row < M::out_r(l)) {
-            const El* gr_ = GZ + db_row * CF::TS;
-            float sacc = 0.0f;
-            for (int hh = 0; hh < CF::WIN; ++hh) {
-              if constexpr (BF) sacc += bf16_f32(gr_[hh]);
-              else sacc += gr_[hh];
-            }
-            db += sacc;
-          }
+          bias_part<BF, M::out_p(l), M::out_r(l), CF::WIN, CF::TS>(GZ, tid, dbp[l]);
           if (has_tile) {
             constexpr int BMT = M::bm(l) / 32;
             constexpr int S = M::out_p(l) / M::KS;
@@ -743,8 +782,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
   }
 
   if constexpr (CF::BWD) {
-    if (db_layer >= 0 && db_row < M::out_r(db_layer))
-      part[(db_layer == 0 ? M::par_b(0) : M::par_b(1)) + db_row] = db;
+    static_assert(M::NL * kThreads * 4 <= kLfH * CF::TS * CF::EB, "bias parts fit in GZ");
+    bias_combine<M>(dbp, reinterpret_cast<float*>(g_lds + CF::L_GZ), part, tid);
   }
 }
 
@@ -769,7 +808,6 @@ struct CCfg {
   static constexpr int XS = M::IN0P + (BF ? 8 : 4);
   static constexpr int TS = WIN + (BF ? 8 : 1);
   static constexpr int XT_ROWS = align32(M::IN0);
-  static constexpr int NB_PER_T = (M::NBIAS + kThreads - 1) / kThreads;
   // LDS: records, X, per-hit out (8 floats), then (backward) the hidden
   // activations [NH][H][TS] (or, with ACT_REG, one staged layer [H][TS] that
   // also takes X^T), X^T [XT_ROWS][TS] and GZ [H][TS]
@@ -825,9 +863,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
     for (int i = tid; i < M::NPARAMS; i += kThreads) part[i] = 0.0f;
     __syncthreads();
   }
-  float db[CF::NB_PER_T];
+  float dbp[M::NL];
 #pragma unroll
-  for (int i = 0; i < CF::NB_PER_T; ++i) db[i] = 0.0f;
+  for (int l = 0; l < M::NL; ++l) dbp[l] = 0.0f;
   float loss_acc = 0.0f;
 
   const int G = gridDim.x, bidx = blockIdx.x;
@@ -1163,21 +1201,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
                          : CF::ACT_REG ? cACT<CF>() + (l == 1 ? CF::L0_ROW * CF::TS : 0)
                                        : cACT<CF>() + (l - 1) * kLfH * CF::TS;
           if (!a.freeze_color) dw_window<BF, M, l, CF::WIN, CF::TS>(GZ, AT, part, wave, lane);
-#pragma unroll
-          for (int bi = 0; bi < CF::NB_PER_T; ++bi) {
-            const int b = tid + bi * kThreads;
-            const int bl = b < M::NH * kLfH ? b / kLfH : M::NH;
-            const int brow = b - bl * kLfH;
-            if (!a.freeze_color && b < M::NBIAS && bl == l && brow < M::out_r(l)) {
-              const El* gr_ = GZ + brow * CF::TS;
-              float sacc = 0.0f;
-              for (int hh = 0; hh < CF::WIN; ++hh) {
-                if constexpr (BF) sacc += bf16_f32(gr_[hh]);
-                else sacc += gr_[hh];
-              }
-              db[bi] += sacc;
-            }
-          }
+          if (!a.freeze_color)
+            bias_part<BF, M::out_p(l), M::out_r(l), CF::WIN, CF::TS>(GZ, tid, dbp[l]);
           if (has_tile) {
             constexpr int BMT = M::bm(l) / 32;
             constexpr int S = M::out_p(l) / M::KS;
@@ -1315,20 +1340,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
   }
 
   if constexpr (CF::BWD) {
-#pragma unroll
-    for (int bi = 0; bi < CF::NB_PER_T; ++bi) {
-      const int b = tid + bi * kThreads;
-      if (b < M::NBIAS) {
-        const int bl = b < M::NH * kLfH ? b / kLfH : M::NH;
-        const int brow = b - bl * kLfH;
-        int pb = 0;
-        static_for<M::NL>([&](auto lc) {
-          constexpr int l = decltype(lc)::value;
-          if (l == bl) pb = M::par_b(l);
-        });
-        part[pb + brow] = db[bi];
-      }
-    }
+    static_assert(M::NL * kThreads * 4 <= kLfH * CF::TS * CF::EB, "bias parts fit in GZ");
+    bias_combine<M>(dbp, reinterpret_cast<float*>(g_lds + CF::L_GZ), part, tid);
     if (MODE == kTrain) {
       const float tot = block_sum<kWaves>(loss_acc, reinterpret_cast<float*>(scr));
       if (tid == 0) a.ws_loss[blockIdx.x] = tot;
