@@ -31,12 +31,19 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// FP32 -> bfloat16 bits, round to nearest even.
+// FP32 -> bfloat16 bits, round to nearest even: gfx950 converts in hardware
+// (v_cvt_pk_bf16_f32, two values per instruction); on every non-NaN input it
+// gives the bits of the integer rounding u + 0x7FFF + ((u >> 16) & 1) >> 16.
+typedef __bf16 bf16x8_vt __attribute__((ext_vector_type(8)));
+typedef float f32x8_vt __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ short bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return static_cast<short>((u >> 16) | 0x40u);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<short>(u >> 16);
+  return __builtin_bit_cast(short, static_cast<__bf16>(x));
+}
+// Eight consecutive values of a tile, packed as one MFMA operand.
+__device__ __forceinline__ s16x8 bf16_rne8(float a0, float a1, float a2, float a3, float a4,
+                                           float a5, float a6, float a7) {
+  const f32x8_vt v = {a0, a1, a2, a3, a4, a5, a6, a7};
+  return __builtin_bit_cast(s16x8, __builtin_convertvector(v, bf16x8_vt));
 }
 __device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 

@@ -209,8 +209,10 @@ __device__ __forceinline__ typename CF::Op d_operand(const f32x16* t, int s) {
   if constexpr (CF::BF) {
     s16x8 b;
     const f32x16& tt = t[s >> 1];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) b[j] = bf16_rne(tt[8 * (s & 1) + j]);
+    {
+      const int o = 8 * (s & 1);
+      b = bf16_rne8(tt[o], tt[o + 1], tt[o + 2], tt[o + 3], tt[o + 4], tt[o + 5], tt[o + 6], tt[o + 7]);
+    }
     return b;
   } else {
     return t[s >> 4][s & 15];
@@ -249,11 +251,8 @@ template <>
 struct ActTile<true> {
   s16x8 lo, hi;
   __device__ __forceinline__ void set(const f32x16& t) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      lo[j] = bf16_rne(t[j]);
-      hi[j] = bf16_rne(t[8 + j]);
-    }
+    lo = bf16_rne8(t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7]);
+    hi = bf16_rne8(t[8], t[9], t[10], t[11], t[12], t[13], t[14], t[15]);
   }
   __device__ __forceinline__ bool positive(int i) const { return (i < 8 ? lo[i] : hi[i - 8]) > 0; }
   __device__ __forceinline__ uint16_t elem(int i) const {
