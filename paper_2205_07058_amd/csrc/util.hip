@@ -10,12 +10,11 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Round-to-nearest-even FP32 -> bfloat16 bits (NaN kept quiet).
+// Round-to-nearest-even FP32 -> bfloat16 bits with gfx950's conversion
+// instruction, the same one the shading kernels use for their operands (a
+// NaN gives a quiet NaN).
 __device__ __forceinline__ uint16_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
 }
 
 int grid_for(int64_t n) {
