@@ -113,7 +113,8 @@ struct Cfg {
   static constexpr int L_GZ = align16(L_OUT + WIN * 32);
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
   static constexpr int L_MAP = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
-  static constexpr int L_SCR = align16(L_MAP + WIN * 4);
+  static constexpr int L_REC2 = align16(L_MAP + WIN * 4);      // backward: records of the
+  static constexpr int L_SCR = align16(L_REC2 + (BWD ? WIN * 64 : 0));  // window awaiting its scatter
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
   static_assert(C <= 32 && CI <= TROWS, "feature gradients come from one 32-row tile");
@@ -145,7 +146,9 @@ struct Smem {
   __device__ __forceinline__ typename CF::Elem* fpack() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_FP); }
   __device__ __forceinline__ typename CF::Elem* bpack() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_BP); }
   __device__ __forceinline__ float* bias() const { return reinterpret_cast<float*>(g_smem + CF::L_BI); }
-  __device__ __forceinline__ RecL* rec() const { return reinterpret_cast<RecL*>(g_smem + CF::L_REC); }
+  __device__ __forceinline__ RecL* rec(int b) const {
+    return reinterpret_cast<RecL*>(g_smem + (b ? CF::L_REC2 : CF::L_REC));
+  }
   __device__ __forceinline__ typename CF::Elem* X() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_X); }
   __device__ __forceinline__ float* out() const { return reinterpret_cast<float*>(g_smem + CF::L_OUT); }
   __device__ __forceinline__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_GZ); }
@@ -391,6 +394,38 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
   const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   const int NB = a.tab.n_blocks;
 
+  // Backward: a window's feature-gradient atomics are issued after the next
+  // window's gather, so that the gather's loads do not queue behind them
+  // (the vector-memory counter a wave waits on counts both); the window's
+  // records stay in the other record buffer, its dL/dx in the GZ region
+  // (untouched until the next window's backward).
+  int rb = 0;                    // record buffer of the current window
+  int pend_tw = 0;               // hits of the window awaiting its scatter
+  float* pend_grad = nullptr;
+  auto scatter = [&](int ptw, float* pgrad, const RecL* prec) {
+    const int n0p = 32 * wave;
+    if (wave < CF::NTILE && n0p < ptw) {
+      constexpr int HPI = 64 / CF::C;            // hits per instruction
+      const int c = lane % CF::C, hs = lane / CF::C;
+      const float* gxs = reinterpret_cast<const float*>(sm.GZ());
+      for (int k = 0; k < 32; k += HPI) {
+        const int hh = n0p + k + hs;
+        if (hh < ptw) {
+          const RecL rc = prec[hh];
+          const int vid[8] = {rc.v0.x, rc.v0.y, rc.v0.z, rc.v0.w, rc.v1.x, rc.v1.y, rc.v1.z, rc.v1.w};
+          const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
+                      wz[2] = {1.0f - rc.uz, rc.uz};
+          const float gv = gxs[hh * CF::C + c];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
+            unsafeAtomicAdd(pgrad + static_cast<int64_t>(vid[j]) * CF::C + c, wj * gv);
+          }
+        }
+      }
+    }
+  };
+
   __syncthreads();
 
   for (int item = lb; item < NB; item += G) {
@@ -400,6 +435,15 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     const int64_t r = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads + tid;
     const bool live = r < sc.ray_end;
     const int count = live ? a.cnt[r] : 0;
+    // the ray's target (train) or upstream gradient (backward), read before
+    // any window so that no load waits behind pending atomics
+    float tg0 = 0.0f, tg1 = 0.0f, tg2 = 0.0f, tg3 = 0.0f, tg4 = 0.0f;
+    if (CF::MODE == kTrain && live) {
+      tg0 = a.t_rgb[3 * r]; tg1 = a.t_rgb[3 * r + 1]; tg2 = a.t_rgb[3 * r + 2]; tg3 = a.t_depth[r];
+    } else if (CF::MODE == kBackward && live) {
+      tg0 = a.g_rgb[3 * r]; tg1 = a.g_rgb[3 * r + 1]; tg2 = a.g_rgb[3 * r + 2]; tg3 = a.g_depth[r];
+      tg4 = a.g_acc ? a.g_acc[r] : 0.0f;
+    }
     const float h = __int_as_float((128 - sc.depth) << 23);       // 2^(1-depth)
     const float inv_h = __int_as_float((126 + sc.depth) << 23);   // 2^(depth-1)
     int total;
@@ -489,7 +533,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
               rc.pad = 0.0f;
               rc.v0 = c0[k];
               rc.v1 = c1[k];
-              sm.rec()[hh[k]] = rc;
+              sm.rec(rb)[hh[k]] = rc;
             }
             const int vid[8] = {c0[k].x, c0[k].y, c0[k].z, c0[k].w, c1[k].x, c1[k].y, c1[k].z, c1[k].w};
             const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
@@ -533,6 +577,11 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
       }
       __syncthreads();
 
+      if constexpr (CF::BWD) {
+        if (pend_tw > 0) scatter(pend_tw, pend_grad, sm.rec(rb ^ 1));
+        pend_tw = 0;
+      }
+
       // decoder on the window: one 32-hit tile per wave
       ActTile<CF::BF> act[CF::NH][CF::MTH];
       const int n0 = 32 * wave;
@@ -542,7 +591,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         // per-hit epilogue, one hit per lane: colour, opacity and
         // transmittance factor of the segment (section 4 footnote, Eq. 3)
         if (g == 0 && n0 + lane < tw) {
-          const RecL& rc = sm.rec()[n0 + lane];
+          const RecL& rc = sm.rec(rb)[n0 + lane];
           const float ft = a.tau_mode == SVLF_TAU_VOXEL ? rc.dt * inv_h
                            : a.tau_mode == SVLF_TAU_WORLD ? rc.dt : 1.0f;
           const float tau = fmaxf(o[3], 0.0f) * ft;
@@ -575,8 +624,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         if constexpr (CF::BWD) {
           float gr, gg, gb, gd, ga;
           if (CF::MODE == kTrain) {
-            const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
-                        eb = cb - a.t_rgb[3 * r + 2], ed = dep - a.t_depth[r];
+            const float er = cr - tg0, eg = cg - tg1, eb = cb - tg2, ed = dep - tg3;
             const float k2 = a.loss_scale * (2.0f / 3.0f);
             gr = k2 * er;
             gg = k2 * eg;
@@ -584,11 +632,11 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
             gd = a.loss_scale * a.lambda_depth * (ed > 0.0f ? 1.0f : (ed < 0.0f ? -1.0f : 0.0f));
             ga = 0.0f;
           } else {
-            gr = a.g_rgb[3 * r];
-            gg = a.g_rgb[3 * r + 1];
-            gb = a.g_rgb[3 * r + 2];
-            gd = a.g_depth[r];
-            ga = a.g_acc ? a.g_acc[r] : 0.0f;
+            gr = tg0;
+            gg = tg1;
+            gb = tg2;
+            gd = tg3;
+            ga = tg4;
           }
           float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f, St = 0.0f, Sa = 0.0f;
           for (int q = count - 1; q >= 0; --q) {
@@ -732,36 +780,30 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
           }
         }
         __syncthreads();
-        if (has_tile) {
-          constexpr int HPI = 64 / CF::C;            // hits per instruction
-          const int c = lane % CF::C, hs = lane / CF::C;
-          for (int k = 0; k < 32; k += HPI) {
-            const int hh = n0 + k + hs;
-            if (hh < tw) {
-              const RecL rc = sm.rec()[hh];
-              const int vid[8] = {rc.v0.x, rc.v0.y, rc.v0.z, rc.v0.w, rc.v1.x, rc.v1.y, rc.v1.z, rc.v1.w};
-              const float wx[2] = {1.0f - rc.ux, rc.ux}, wy[2] = {1.0f - rc.uy, rc.uy},
-                          wz[2] = {1.0f - rc.uz, rc.uz};
-              const float gv = gxs[hh * CF::C + c];
-              if (a.gxu != nullptr) {
-                // deterministic mode: keep (u, dL/dx) per hit slot; the
-                // feature gradient is reduced afterwards in a fixed order
+        if (a.gxu != nullptr) {
+          // deterministic mode: keep (u, dL/dx) per hit slot; the feature
+          // gradient is reduced afterwards in a fixed order
+          if (has_tile) {
+            constexpr int HPI = 64 / CF::C;
+            const int c = lane % CF::C, hs = lane / CF::C;
+            for (int k = 0; k < 32; k += HPI) {
+              const int hh = n0 + k + hs;
+              if (hh < tw) {
+                const RecL rc = sm.rec(rb)[hh];
                 const int mp = sm.hmap()[hh];
                 const int64_t slot =
                     (sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads + (mp & 0xFFFF)) * a.K +
                     (mp >> 16);
                 float* rec_out = a.gxu + slot * (CF::C + 4);
-                rec_out[4 + c] = gv;
+                rec_out[4 + c] = gxs[hh * CF::C + c];
                 if (c < 3) rec_out[c] = c == 0 ? rc.ux : (c == 1 ? rc.uy : rc.uz);
-              } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                  const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
-                  unsafeAtomicAdd(sc.grad + static_cast<int64_t>(vid[j]) * CF::C + c, wj * gv);
-                }
               }
             }
           }
+        } else {
+          pend_tw = tw;
+          pend_grad = sc.grad;
+          rb ^= 1;
         }
       }
       __syncthreads();
@@ -779,8 +821,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         if (a.acc) a.acc[r] = acc;
       }
       if (CF::MODE == kTrain) {
-        const float er = cr - a.t_rgb[3 * r], eg = cg - a.t_rgb[3 * r + 1],
-                    eb = cb - a.t_rgb[3 * r + 2], ed = dep - a.t_depth[r];
+        const float er = cr - tg0, eg = cg - tg1, eb = cb - tg2, ed = dep - tg3;
         loss_acc += a.loss_scale * ((er * er + eg * eg + eb * eb) * (1.0f / 3.0f) +
                                     a.lambda_depth * fabsf(ed));
       }
@@ -788,6 +829,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
   }
 
   if constexpr (CF::BWD) {
+    if (pend_tw > 0) scatter(pend_tw, pend_grad, sm.rec(rb ^ 1));
     // this block's partial sums of dL/dparams (every entry written once)
     float* part = a.ws_partials + static_cast<int64_t>(blockIdx.x) * CF::NPARAMS;
     static_for<CF::NL>([&](auto lc) {
