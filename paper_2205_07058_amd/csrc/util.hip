@@ -110,20 +110,48 @@ __global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ d, float 
 
 // out[j] += sum over rows r (in order) of partials[r][j]; loss_out = sum of
 // loss partials.  Fixed order: deterministic.
+// Sum of `rows` per-block partial vectors (row-major [rows][n]) into out.
+// A block owns 64 columns; thread (column, quarter) sums its quarter of the
+// rows in order, the four quarter sums are then added in order: a fixed
+// summation order for any launch.  Block 0 also sums the loss partials.
+constexpr int kRedCols = 64;
 __global__ __launch_bounds__(kThreads) void k_reduce(const float* __restrict__ part, int rows,
                                                      int64_t n, float* __restrict__ out,
                                                      const float* __restrict__ lp,
                                                      float* __restrict__ loss_out) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
-  for (int64_t j = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; j < n; j += stride) {
+  __shared__ float q[kThreads];
+  const int t = threadIdx.x, col = t % kRedCols, qt = t / kRedCols;
+  constexpr int NQ = kThreads / kRedCols;
+  const int r0 = static_cast<int>(static_cast<int64_t>(rows) * qt / NQ);
+  const int r1 = static_cast<int>(static_cast<int64_t>(rows) * (qt + 1) / NQ);
+  for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * kRedCols; c0 < n;
+       c0 += static_cast<int64_t>(gridDim.x) * kRedCols) {
+    const int64_t j = c0 + col;
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += part[static_cast<int64_t>(r) * n + j];
-    out[j] += s;
+    if (j < n) {
+#pragma unroll 8
+      for (int r = r0; r < r1; ++r) s += part[static_cast<int64_t>(r) * n + j];
+    }
+    q[t] = s;
+    __syncthreads();
+    if (qt == 0 && j < n) {
+      float tot = q[col];
+#pragma unroll
+      for (int k = 1; k < NQ; ++k) tot += q[k * kRedCols + col];
+      out[j] += tot;
+    }
+    __syncthreads();
   }
-  if (loss_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (loss_out != nullptr && blockIdx.x == 0) {
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += lp[r];
-    *loss_out = s;
+    for (int r = t; r < rows; r += kThreads) s += lp[r];
+    q[t] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (t < w) q[t] += q[t + w];
+      __syncthreads();
+    }
+    if (t == 0) *loss_out = q[0];
   }
 }
 
@@ -164,8 +192,11 @@ hipError_t launch_fill(float* dst, float v, int64_t n, hipStream_t s) {
 
 hipError_t launch_reduce_partials(const float* partials, int rows, int64_t n, float* out,
                                   const float* loss_partials, float* loss_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n)), dim3(kThreads), 0, s, partials, rows, n, out,
-                     loss_partials, loss_out);
+  int64_t blocks = (n + kRedCols - 1) / kRedCols;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_reduce, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, partials,
+                     rows, n, out, loss_partials, loss_out);
   return hipGetLastError();
 }
 
