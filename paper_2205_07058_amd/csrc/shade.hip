@@ -114,7 +114,8 @@ struct Cfg {
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
   static constexpr int L_MAP = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
   static constexpr int L_REC2 = align16(L_MAP + WIN * 4);      // backward: records of the
-  static constexpr int L_SCR = align16(L_REC2 + (BWD ? WIN * 64 : 0));  // window awaiting its scatter
+  static constexpr int L_MAP2 = align16(L_REC2 + (BWD ? WIN * 64 : 0));  // window awaiting its
+  static constexpr int L_SCR = align16(L_MAP2 + (BWD ? WIN * 4 : 0));   // scatter; next window's map
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
   static_assert(C <= 32 && CI <= TROWS, "feature gradients come from one 32-row tile");
@@ -154,7 +155,9 @@ struct Smem {
   __device__ __forceinline__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_GZ); }
   __device__ __forceinline__ typename CF::Elem* AT() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_AT); }
   __device__ __forceinline__ int* scr() const { return reinterpret_cast<int*>(g_smem + CF::L_SCR); }
-  __device__ __forceinline__ int* hmap() const { return reinterpret_cast<int*>(g_smem + CF::L_MAP); }
+  __device__ __forceinline__ int* hmap(int b) const {
+    return reinterpret_cast<int*>(g_smem + (b ? CF::L_MAP2 : CF::L_MAP));
+  }
 };
 
 template <class CF>
@@ -450,129 +453,171 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     const int off = block_excl_scan<kWaves>(count, sm.scr(), total);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, acc = 0.0f;
 
-    int s0 = 0;
-    while (s0 < total) {
-      // the window: rays whose hits all fit in [s0, s0 + WIN)
+    const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
+    // Window: the rays whose hits all fit in [w0, w0 + WIN); the ray's lane
+    // alone publishes its map entries (window hit -> ray lane, slot) into
+    // hit map `hb`.  Returns the window's end; `inw` = this ray is in it.
+    auto open_win = [&](int w0, int hb, bool& inw) -> int {
       if (tid == 0) sm.scr()[8] = total;
       __syncthreads();
-      const bool started = count > 0 && off >= s0;
-      const bool in_win = started && off + count <= s0 + CF::WIN;
-      if (started && !in_win) atomicMin(&sm.scr()[8], off);
+      const bool started = count > 0 && off >= w0;
+      inw = started && off + count <= w0 + CF::WIN;
+      if (started && !inw) atomicMin(&sm.scr()[8], off);
       __syncthreads();
-      const int s1 = sm.scr()[8];
-      const int tw = s1 - s0;
-      // window hit h -> (ray lane, slot): the ray's lane only publishes the map
-      if (in_win) {
-        for (int q = 0; q < count; ++q) sm.hmap()[off - s0 + q] = tid | (q << 16);
+      const int w1 = sm.scr()[8];
+      if (inw) {
+        for (int q = 0; q < count; ++q) sm.hmap(hb)[off - w0 + q] = tid | (q << 16);
       }
       __syncthreads();
+      return w1;
+    };
+    // Gather in three dependent stages: (A) hit records and rays, (B) the
+    // leaves' corner ids, (C) trilinear weights and the 8 corner rows -> X.
+    // A thread serves GRP hits (all the window's hits in one group).  In the
+    // backward kernels windows are opened one ahead and the next window's
+    // stage A is issued before this window's stage C, its stage B after the
+    // forward decoder, so that the gather waits on one level of loads only.
+    constexpr int ROWB = CF::C * CF::EB;
+    constexpr int TPH = ROWB / 16;
+    constexpr int VPT = 16 / CF::EB;             // values per thread
+    constexpr int HPP = kThreads / TPH;
+    constexpr int NPASS = (CF::WIN + HPP - 1) / HPP;
+    constexpr int GRP = (CF::BWD && NPASS >= 2) ? 2 : 1;
+    constexpr bool PIPE = CF::BWD;
+    static_assert(!PIPE || NPASS == GRP, "one gather group per window");
+    const int q = tid % TPH;
+    struct Stage {
+      int hh[GRP];
+      bool val[GRP];
+      HitRec hr[GRP];
+      float ro[GRP][3], rd[GRP][3];
+      int4 c0[GRP], c1[GRP];
+    };
+    auto stage_a = [&](Stage& st, int pb, int hb, int twin) {
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+        st.hh[k] = (pb + k) * HPP + tid / TPH;
+        st.val[k] = st.hh[k] < twin;
+        if (st.val[k]) {
+          const int mp = sm.hmap(hb)[st.hh[k]];
+          const int64_t rr = ray0 + (mp & 0xFFFF);
+          st.hr[k] = a.hits[rr * a.K + (mp >> 16)];
+          st.ro[k][0] = a.o[3 * rr]; st.ro[k][1] = a.o[3 * rr + 1]; st.ro[k][2] = a.o[3 * rr + 2];
+          st.rd[k][0] = a.d[3 * rr]; st.rd[k][1] = a.d[3 * rr + 1]; st.rd[k][2] = a.d[3 * rr + 2];
+        }
+      }
+    };
+    auto stage_b = [&](Stage& st) {
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+        if (st.val[k]) {
+          const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(st.hr[k].leaf));
+          st.c0[k] = lc[0];
+          st.c1[k] = lc[1];
+        }
+      }
+    };
+    auto stage_c = [&](Stage& st) {
+      float v[GRP][VPT];
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) v[k][i] = 0.0f;
+        if (!st.val[k]) continue;
+        const float tm = 0.5f * (st.hr[k].tin + st.hr[k].tout);
+        const float lx = -1.0f + static_cast<float>(st.hr[k].ijk & 1023u) * h;
+        const float ly = -1.0f + static_cast<float>((st.hr[k].ijk >> 10) & 1023u) * h;
+        const float lz = -1.0f + static_cast<float>(st.hr[k].ijk >> 20) * h;
+        const float ux = fminf(fmaxf((st.ro[k][0] + tm * st.rd[k][0] - lx) * inv_h, 0.0f), 1.0f);
+        const float uy = fminf(fmaxf((st.ro[k][1] + tm * st.rd[k][1] - ly) * inv_h, 0.0f), 1.0f);
+        const float uz = fminf(fmaxf((st.ro[k][2] + tm * st.rd[k][2] - lz) * inv_h, 0.0f), 1.0f);
+        if (q == 0) {
+          RecL rc;
+          rc.leaf = st.hr[k].leaf;
+          rc.ux = ux;
+          rc.uy = uy;
+          rc.uz = uz;
+          rc.tmid = tm;
+          rc.dt = st.hr[k].tout - st.hr[k].tin;
+          rc.T = 0.0f;
+          rc.pad = 0.0f;
+          rc.v0 = st.c0[k];
+          rc.v1 = st.c1[k];
+          sm.rec(rb)[st.hh[k]] = rc;
+        }
+        const int vid[8] = {st.c0[k].x, st.c0[k].y, st.c0[k].z, st.c0[k].w,
+                            st.c1[k].x, st.c1[k].y, st.c1[k].z, st.c1[k].w};
+        const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
+          if constexpr (CF::BF) {
+            const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * CF::C + 8 * q);
+            const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              v[k][2 * i] += wj * bf16_f32(static_cast<uint16_t>(w4[i] & 0xFFFFu));
+              v[k][2 * i + 1] += wj * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
+            }
+          } else {
+            const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * CF::C + 4 * q);
+            v[k][0] += wj * f.x;
+            v[k][1] += wj * f.y;
+            v[k][2] += wj * f.z;
+            v[k][3] += wj * f.w;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+        if (st.hh[k] >= CF::WIN) continue;
+        typename CF::Elem* xr = sm.X() + st.hh[k] * CF::XS + VPT * q;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) xr[i] = to_elem<CF>(v[k][i]);
+        if (CF::CI > CF::C && q == 0) {
+          // view direction (VD) and zero padding up to the K steps
+#pragma unroll
+          for (int i = CF::C; i < CF::CI; ++i) {
+            float xv = 0.0f;
+            if (CF::VD && i < CF::C + 3 && st.val[k]) xv = st.rd[k][i - CF::C];
+            sm.X()[st.hh[k] * CF::XS + i] = to_elem<CF>(xv);
+          }
+        }
+      }
+    };
 
-      // per hit, in parallel: hit record, ray, corner ids, trilinear weights
-      // and the gather of the 8 corner rows -> X[h][0..CI); the first thread
-      // of each hit also writes the LDS hit record.  A thread serves NPASS
-      // hits; the loads of a group of passes are all issued before any is
-      // consumed.
-      {
-        constexpr int ROWB = CF::C * CF::EB;
-        constexpr int TPH = ROWB / 16;
-        constexpr int VPT = 16 / CF::EB;           // values per thread
-        constexpr int HPP = kThreads / TPH;
-        constexpr int NPASS = (CF::WIN + HPP - 1) / HPP;
-        constexpr int GRP = (CF::BWD && NPASS >= 2) ? 2 : 1;
-        const int q = tid % TPH;
-        const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
+    Stage cur, nxt;
+    int hb = 0;                    // hit map of the current window
+    bool have_next = false;        // nxt holds stages A and B of the next window
+    bool in_win_n = false;
+    int s1n = 0;
+    int s0 = 0;
+    while (s0 < total) {
+      bool in_win;
+      int s1;
+      if (have_next) {
+        cur = nxt;
+        in_win = in_win_n;
+        s1 = s1n;
+      } else {
+        s1 = open_win(s0, hb, in_win);
+      }
+      const int tw = s1 - s0;
+      const bool pre = PIPE && s1 < total;
+      if (pre) s1n = open_win(s1, hb ^ 1, in_win_n);
+      if (PIPE) {
+        if (!have_next) {
+          stage_a(cur, 0, hb, tw);
+          stage_b(cur);
+        }
+        if (pre) stage_a(nxt, 0, hb ^ 1, s1n - s1);
+        stage_c(cur);
+      } else {
 #pragma unroll 1
         for (int pb = 0; pb < NPASS; pb += GRP) {
-          int hh[GRP];
-          bool val[GRP];
-          HitRec hr[GRP];
-          float ro[GRP][3], rd[GRP][3];
-          int4 c0[GRP], c1[GRP];
-#pragma unroll
-          for (int k = 0; k < GRP; ++k) {
-            hh[k] = (pb + k) * HPP + tid / TPH;
-            val[k] = hh[k] < tw;
-            if (val[k]) {
-              const int mp = sm.hmap()[hh[k]];
-              const int64_t rr = ray0 + (mp & 0xFFFF);
-              hr[k] = a.hits[rr * a.K + (mp >> 16)];
-              ro[k][0] = a.o[3 * rr]; ro[k][1] = a.o[3 * rr + 1]; ro[k][2] = a.o[3 * rr + 2];
-              rd[k][0] = a.d[3 * rr]; rd[k][1] = a.d[3 * rr + 1]; rd[k][2] = a.d[3 * rr + 2];
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < GRP; ++k) {
-            if (val[k]) {
-              const int4* lc = reinterpret_cast<const int4*>(sc.leaf_corners + 8 * static_cast<int64_t>(hr[k].leaf));
-              c0[k] = lc[0];
-              c1[k] = lc[1];
-            }
-          }
-          float v[GRP][VPT];
-#pragma unroll
-          for (int k = 0; k < GRP; ++k) {
-#pragma unroll
-            for (int i = 0; i < VPT; ++i) v[k][i] = 0.0f;
-            if (!val[k]) continue;
-            const float tm = 0.5f * (hr[k].tin + hr[k].tout);
-            const float lx = -1.0f + static_cast<float>(hr[k].ijk & 1023u) * h;
-            const float ly = -1.0f + static_cast<float>((hr[k].ijk >> 10) & 1023u) * h;
-            const float lz = -1.0f + static_cast<float>(hr[k].ijk >> 20) * h;
-            const float ux = fminf(fmaxf((ro[k][0] + tm * rd[k][0] - lx) * inv_h, 0.0f), 1.0f);
-            const float uy = fminf(fmaxf((ro[k][1] + tm * rd[k][1] - ly) * inv_h, 0.0f), 1.0f);
-            const float uz = fminf(fmaxf((ro[k][2] + tm * rd[k][2] - lz) * inv_h, 0.0f), 1.0f);
-            if (q == 0) {
-              RecL rc;
-              rc.leaf = hr[k].leaf;
-              rc.ux = ux;
-              rc.uy = uy;
-              rc.uz = uz;
-              rc.tmid = tm;
-              rc.dt = hr[k].tout - hr[k].tin;
-              rc.T = 0.0f;
-              rc.pad = 0.0f;
-              rc.v0 = c0[k];
-              rc.v1 = c1[k];
-              sm.rec(rb)[hh[k]] = rc;
-            }
-            const int vid[8] = {c0[k].x, c0[k].y, c0[k].z, c0[k].w, c1[k].x, c1[k].y, c1[k].z, c1[k].w};
-            const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
-              if constexpr (CF::BF) {
-                const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * CF::C + 8 * q);
-                const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                  v[k][2 * i] += wj * bf16_f32(static_cast<uint16_t>(w4[i] & 0xFFFFu));
-                  v[k][2 * i + 1] += wj * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
-                }
-              } else {
-                const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * CF::C + 4 * q);
-                v[k][0] += wj * f.x;
-                v[k][1] += wj * f.y;
-                v[k][2] += wj * f.z;
-                v[k][3] += wj * f.w;
-              }
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < GRP; ++k) {
-            if (hh[k] >= CF::WIN) continue;
-            typename CF::Elem* xr = sm.X() + hh[k] * CF::XS + VPT * q;
-#pragma unroll
-            for (int i = 0; i < VPT; ++i) xr[i] = to_elem<CF>(v[k][i]);
-            if (CF::CI > CF::C && q == 0) {
-              // view direction (VD) and zero padding up to the K steps
-#pragma unroll
-              for (int i = CF::C; i < CF::CI; ++i) {
-                float xv = 0.0f;
-                if (CF::VD && i < CF::C + 3 && val[k]) xv = rd[k][i - CF::C];
-                sm.X()[hh[k] * CF::XS + i] = to_elem<CF>(xv);
-              }
-            }
-          }
+          stage_a(cur, pb, hb, tw);
+          stage_b(cur);
+          stage_c(cur);
         }
       }
       __syncthreads();
@@ -601,6 +646,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
           *reinterpret_cast<f32x4*>(sm.out() + 8 * (n0 + lane) + 4) = vb;
         }
       }
+      if (pre) stage_b(nxt);
       __syncthreads();
 
       // Eq. 3 front to back (owner lanes), and its backward
@@ -790,7 +836,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
               const int hh = n0 + k + hs;
               if (hh < tw) {
                 const RecL rc = sm.rec(rb)[hh];
-                const int mp = sm.hmap()[hh];
+                const int mp = sm.hmap(hb)[hh];
                 const int64_t slot =
                     (sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads + (mp & 0xFFFF)) * a.K +
                     (mp >> 16);
@@ -808,6 +854,8 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
       }
       __syncthreads();
       s0 = s1;
+      have_next = pre;
+      if (pre) hb ^= 1;
     }
 
     if (live) {
