@@ -113,9 +113,11 @@ struct Cfg {
   static constexpr int L_GZ = align16(L_OUT + WIN * 32);
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
   static constexpr int L_MAP = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
-  static constexpr int L_REC2 = align16(L_MAP + WIN * 4);      // backward: records of the
-  static constexpr int L_MAP2 = align16(L_REC2 + (BWD ? WIN * 64 : 0));  // window awaiting its
-  static constexpr int L_SCR = align16(L_MAP2 + (BWD ? WIN * 4 : 0));   // scatter; next window's map
+  // backward: records of the window awaiting its scatter, the next window's
+  // hit map
+  static constexpr int L_REC2 = align16(L_MAP + WIN * 4);
+  static constexpr int L_MAP2 = align16(L_REC2 + (BWD ? WIN * 64 : 0));
+  static constexpr int L_SCR = align16(L_MAP2 + (BWD ? WIN * 4 : 0));
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
   static_assert(C <= 32 && CI <= TROWS, "feature gradients come from one 32-row tile");
@@ -473,17 +475,18 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     };
     // Gather in three dependent stages: (A) hit records and rays, (B) the
     // leaves' corner ids, (C) trilinear weights and the 8 corner rows -> X.
-    // A thread serves GRP hits (all the window's hits in one group).  In the
-    // backward kernels windows are opened one ahead and the next window's
-    // stage A is issued before this window's stage C, its stage B after the
-    // forward decoder, so that the gather waits on one level of loads only.
+    // A thread serves GRP hits (in the backward kernels one group covers the
+    // window).  There (PIPE) windows are opened one ahead and the next
+    // window's stage A is issued before this window's stage C, its stage B
+    // after the forward decoder, so that the gather waits on one level of
+    // loads only.
     constexpr int ROWB = CF::C * CF::EB;
     constexpr int TPH = ROWB / 16;
     constexpr int VPT = 16 / CF::EB;             // values per thread
     constexpr int HPP = kThreads / TPH;
     constexpr int NPASS = (CF::WIN + HPP - 1) / HPP;
     constexpr int GRP = (CF::BWD && NPASS >= 2) ? 2 : 1;
-    constexpr bool PIPE = CF::BWD;
+    constexpr bool PIPE = CF::BWD;   // forward kernels: slower so (at their register cap)
     static_assert(!PIPE || NPASS == GRP, "one gather group per window");
     const int q = tid % TPH;
     struct Stage {
@@ -983,7 +986,14 @@ hipError_t run(const ShadeArgs& a, hipStream_t s, int* grid_used) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, CF::LDS_BYTES);
   if (e != hipSuccess) return e;
-  const int per_cu = (160 * 1024) / CF::LDS_BYTES;
+  // resident blocks per CU: LDS and registers (the persistent grid must fit
+  // in one round, or the blocks of a second round would run after the rest)
+  int per_cu = (160 * 1024) / CF::LDS_BYTES;
+  static int occ = -1;                         // per kernel instance, queried once
+  if (occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     &occ, reinterpret_cast<const void*>(kern), kThreads, CF::LDS_BYTES) != hipSuccess)
+    occ = 0;
+  if (occ > 0 && occ < per_cu) per_cu = occ;
   int grid = num_cus() * (per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu));
   if (grid > shade_grid_limit()) grid = shade_grid_limit();
   if (grid > a.tab.n_blocks) grid = a.tab.n_blocks;
