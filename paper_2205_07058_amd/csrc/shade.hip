@@ -162,6 +162,34 @@ struct Smem {
   }
 };
 
+// The segment midpoint t = (t0 + t1) / 2 as an unevaluated sum hi + lo
+// (TwoSum, exact), and the cell coordinate (o + t d - lo_plane) / h of the
+// point there, evaluated with error-free transformations (TwoSum, FMA
+// residual of the product): its error stays a few ulps of the result even
+// when the origin lies far from the cell, where plain binary32 evaluation
+// loses about |o| 2^-24 absolutely and 1/h (up to 2^9) scales that up.
+__device__ __forceinline__ void midpoint2(float t0, float t1, float& hi, float& lo) {
+#pragma clang fp contract(off)
+  const float s = t0 + t1;
+  const float v = s - t0;
+  const float e = (t0 - (s - v)) + (t1 - v);
+  hi = 0.5f * s;
+  lo = 0.5f * e;
+}
+__device__ __forceinline__ float cell_coord(float o, float d, float thi, float tlo, float plane,
+                                            float inv_h) {
+#pragma clang fp contract(off)
+  const float a = o - plane;
+  const float av = a - o;
+  const float ea = (o - (a - av)) + (-plane - av);
+  const float b = thi * d;
+  const float eb = __builtin_fmaf(thi, d, -b);
+  const float s = a + b;
+  const float sv = s - a;
+  const float es = (a - (s - sv)) + (b - sv);
+  return (s + (((ea + eb) + es) + tlo * d)) * inv_h;
+}
+
 template <class CF>
 __device__ __forceinline__ typename CF::Elem to_elem(float v) {
   if constexpr (CF::BF) return static_cast<uint16_t>(bf16_rne(v));
@@ -527,13 +555,14 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
 #pragma unroll
         for (int i = 0; i < VPT; ++i) v[k][i] = 0.0f;
         if (!st.val[k]) continue;
-        const float tm = 0.5f * (st.hr[k].tin + st.hr[k].tout);
+        float tm, tml;
+        midpoint2(st.hr[k].tin, st.hr[k].tout, tm, tml);
         const float lx = -1.0f + static_cast<float>(st.hr[k].ijk & 1023u) * h;
         const float ly = -1.0f + static_cast<float>((st.hr[k].ijk >> 10) & 1023u) * h;
         const float lz = -1.0f + static_cast<float>(st.hr[k].ijk >> 20) * h;
-        const float ux = fminf(fmaxf((st.ro[k][0] + tm * st.rd[k][0] - lx) * inv_h, 0.0f), 1.0f);
-        const float uy = fminf(fmaxf((st.ro[k][1] + tm * st.rd[k][1] - ly) * inv_h, 0.0f), 1.0f);
-        const float uz = fminf(fmaxf((st.ro[k][2] + tm * st.rd[k][2] - lz) * inv_h, 0.0f), 1.0f);
+        const float ux = fminf(fmaxf(cell_coord(st.ro[k][0], st.rd[k][0], tm, tml, lx, inv_h), 0.0f), 1.0f);
+        const float uy = fminf(fmaxf(cell_coord(st.ro[k][1], st.rd[k][1], tm, tml, ly, inv_h), 0.0f), 1.0f);
+        const float uz = fminf(fmaxf(cell_coord(st.ro[k][2], st.rd[k][2], tm, tml, lz, inv_h), 0.0f), 1.0f);
         if (q == 0) {
           RecL rc;
           rc.leaf = st.hr[k].leaf;

@@ -334,3 +334,63 @@ def test_max_K_solid_scene(gpu_lib):
     leF, lep = render_lf_backward(lst2, lg_rgb, lg_dep)
     assert_grad_close(lgF, leF, "K16 lf grad_features")
     assert_grad_close(lgp, lep, "K16 lf grad_params", rel_nw=1e-4, rel_el=None)
+
+
+def test_depth_10_scene(gpu_lib):
+    """The deepest supported octree (depth 10: 1024^3 leaf grid, 10-bit cell
+    coordinates, plane spacing 2^-9): clusters of leaves, including cells on
+    the grid's faces and corners, and rays aimed at them.  Hit lists
+    bit-exact, FP32 render and gradients against the oracle."""
+    from oracle.octree import Octree
+    from oracle.trace import trace_hits as oracle_trace
+    rng = np.random.default_rng(1010)
+    depth = 10
+    n = 1 << depth
+    centres = rng.integers(0, n, (24, 3))
+    centres[:4] = [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, n // 2], [n // 2, 0, n - 1]]
+    blk = np.stack(np.meshgrid(*[np.arange(-2, 3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    cells = np.concatenate([np.clip(c + blk[rng.random(blk.shape[0]) < 0.5], 0, n - 1)
+                            for c in centres])
+    cells = np.unique(cells, axis=0).astype(np.int32)
+    nv = Octree(cells, depth).n_vertices
+    widths = (16, 64, 64, 64, 4)
+    F = rng.normal(0.0, 1.0, (nv, 16)).astype(np.float32)
+    p = xavier_params(np.random.default_rng(7), widths)
+    p[-1] = 0.5
+    case = Case(gpu_lib, cells, depth, F, p, widths, 8)
+    # rays from a sphere of radius 3 towards the clusters (jittered by a few
+    # cells), plus random rays
+    m = 3000
+    tgt = -1.0 + (centres[rng.integers(0, len(centres), m)] + 0.5 + rng.uniform(-3, 3, (m, 3))) * (2.0 / n)
+    v = rng.standard_normal((m, 3))
+    o = 3.0 * v / np.linalg.norm(v, axis=1, keepdims=True)
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o2, d2 = random_rays(rng, 1000, inside_frac=0.3)
+    o = np.concatenate([o, o2]).astype(np.float32)
+    d = np.concatenate([d, d2]).astype(np.float32)
+    # hit lists
+    import torch
+    to, td = case.rays(o, d)
+    leaf, tin, tout, cnt = gpu_lib.trace_hits(case.scene.octree, to, td, 8)
+    torch.cuda.synchronize()
+    el, ei, eo, ec = oracle_trace(case.oc, o, d, 8)
+    np.testing.assert_array_equal(cnt.cpu().numpy(), ec)
+    np.testing.assert_array_equal(leaf.cpu().numpy(), el)
+    np.testing.assert_array_equal(tin.cpu().numpy().view(np.int32), ei.view(np.int32))
+    np.testing.assert_array_equal(tout.cpu().numpy().view(np.int32), eo.view(np.int32))
+    assert ec.sum() > 3000 and (ec > 0).mean() > 0.3
+    # render and gradients
+    rgb, dep, acc = case.gpu_render(o, d)
+    er, ed, ea, _ = case.oracle(o, d)
+    assert_outputs_close(rgb, er, 1.0, "depth 10 rgb")
+    assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), "depth 10 depth")
+    assert_outputs_close(acc, ea, 1.0, "depth 10 acc")
+    keep = case.smooth_rays(o, d)
+    g_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)
+    g_dep = rng.normal(size=keep.size).astype(np.float32)
+    gF, gp = _gpu_backward(case, o[keep], d[keep], g_rgb, g_dep, None)
+    _, _, _, st = case.oracle(o[keep], d[keep])
+    eF, ep = render_backward(st, g_rgb, g_dep)
+    assert_grad_close(gF, eF, "depth 10 grad_features")
+    assert_grad_close(gp, ep, "depth 10 grad_params", rel_nw=1e-4, rel_el=None)
