@@ -505,12 +505,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
             const float ly = -1.0f + static_cast<float>((hr.ijk >> 10) & 1023u) * h;
             const float lz = -1.0f + static_cast<float>(hr.ijk >> 20) * h;
             DRec rc;
-            rc.u1[0] = (fmaf(hr.tin, dx, ox) - lx) * inv_h;
-            rc.u1[1] = (fmaf(hr.tin, dy, oy) - ly) * inv_h;
-            rc.u1[2] = (fmaf(hr.tin, dz, oz) - lz) * inv_h;
-            rc.u2[0] = (fmaf(hr.tout, dx, ox) - lx) * inv_h;
-            rc.u2[1] = (fmaf(hr.tout, dy, oy) - ly) * inv_h;
-            rc.u2[2] = (fmaf(hr.tout, dz, oz) - lz) * inv_h;
+            rc.u1[0] = cell_coord(ox, dx, hr.tin, 0.0f, lx, inv_h);
+            rc.u1[1] = cell_coord(oy, dy, hr.tin, 0.0f, ly, inv_h);
+            rc.u1[2] = cell_coord(oz, dz, hr.tin, 0.0f, lz, inv_h);
+            rc.u2[0] = cell_coord(ox, dx, hr.tout, 0.0f, lx, inv_h);
+            rc.u2[1] = cell_coord(oy, dy, hr.tout, 0.0f, ly, inv_h);
+            rc.u2[2] = cell_coord(oz, dz, hr.tout, 0.0f, lz, inv_h);
             rc.tin = hr.tin;
             rc.tout = hr.tout;
             rc.v0 = lc[0];
@@ -553,10 +553,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
             const float lx = -1.0f + static_cast<float>(hr.ijk & 1023u) * h;
             const float ly = -1.0f + static_cast<float>((hr.ijk >> 10) & 1023u) * h;
             const float lz = -1.0f + static_cast<float>(hr.ijk >> 20) * h;
-            const float x1[3] = {fmaf(hr.tin, dx, ox), fmaf(hr.tin, dy, oy), fmaf(hr.tin, dz, oz)};
-            const float x2[3] = {fmaf(hr.tout, dx, ox), fmaf(hr.tout, dy, oy), fmaf(hr.tout, dz, oz)};
-            const float u1[3] = {(x1[0] - lx) * inv_h, (x1[1] - ly) * inv_h, (x1[2] - lz) * inv_h};
-            const float u2[3] = {(x2[0] - lx) * inv_h, (x2[1] - ly) * inv_h, (x2[2] - lz) * inv_h};
+            const float u1[3] = {cell_coord(ox, dx, hr.tin, 0.0f, lx, inv_h),
+                                 cell_coord(oy, dy, hr.tin, 0.0f, ly, inv_h),
+                                 cell_coord(oz, dz, hr.tin, 0.0f, lz, inv_h)};
+            const float u2[3] = {cell_coord(ox, dx, hr.tout, 0.0f, lx, inv_h),
+                                 cell_coord(oy, dy, hr.tout, 0.0f, ly, inv_h),
+                                 cell_coord(oz, dz, hr.tout, 0.0f, lz, inv_h)};
             if (q == 0) {
               DRec rc;
               rc.u1[0] = u1[0]; rc.u1[1] = u1[1]; rc.u1[2] = u1[2];
@@ -567,7 +569,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
               rc.v1 = c1;
               rec[hh] = rc;
               const float hc = 0.5f * h;
-              sphere_r(x1[0] - (lx + hc), x1[1] - (ly + hc), x1[2] - (lz + hc), dx, dy, dz, h, rr);
+              sphere_r(cell_coord(ox, dx, hr.tin, 0.0f, lx + hc, 1.0f),
+                       cell_coord(oy, dy, hr.tin, 0.0f, ly + hc, 1.0f),
+                       cell_coord(oz, dz, hr.tin, 0.0f, lz + hc, 1.0f), dx, dy, dz, h, rr);
             }
             float w1[8], w2[8];
             trilinear(clamp01(u1[0]), clamp01(u1[1]), clamp01(u1[2]), w1);
@@ -929,8 +933,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
               const float lz = -1.0f + static_cast<float>(hr.ijk >> 20) * h;
               const float hc = 0.5f * h;
               float r6[6];
-              sphere_r(fmaf(hr.tin, dx, ox) - (lx + hc), fmaf(hr.tin, dy, oy) - (ly + hc),
-                       fmaf(hr.tin, dz, oz) - (lz + hc), dx, dy, dz, h, r6);
+              sphere_r(cell_coord(ox, dx, hr.tin, 0.0f, lx + hc, 1.0f),
+                       cell_coord(oy, dy, hr.tin, 0.0f, ly + hc, 1.0f),
+                       cell_coord(oz, dz, hr.tin, 0.0f, lz + hc, 1.0f), dx, dy, dz, h, r6);
 #pragma unroll
               for (int i = 0; i < 6; ++i) rr[i] = r6[i];
               rr[6] = dx;

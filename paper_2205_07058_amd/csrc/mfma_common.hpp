@@ -47,6 +47,34 @@ __device__ __forceinline__ s16x8 bf16_rne8(float a0, float a1, float a2, float a
 }
 __device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
+// The segment midpoint t = (t0 + t1) / 2 as an unevaluated sum hi + lo
+// (TwoSum, exact), and the cell coordinate (o + t d - lo_plane) / h of the
+// point there, evaluated with error-free transformations (TwoSum, FMA
+// residual of the product): its error stays a few ulps of the result even
+// when the origin lies far from the cell, where plain binary32 evaluation
+// loses about |o| 2^-24 absolutely and 1/h (up to 2^9) scales that up.
+__device__ __forceinline__ void midpoint2(float t0, float t1, float& hi, float& lo) {
+#pragma clang fp contract(off)
+  const float s = t0 + t1;
+  const float v = s - t0;
+  const float e = (t0 - (s - v)) + (t1 - v);
+  hi = 0.5f * s;
+  lo = 0.5f * e;
+}
+__device__ __forceinline__ float cell_coord(float o, float d, float thi, float tlo, float plane,
+                                            float inv_h) {
+#pragma clang fp contract(off)
+  const float a = o - plane;
+  const float av = a - o;
+  const float ea = (o - (a - av)) + (-plane - av);
+  const float b = thi * d;
+  const float eb = __builtin_fmaf(thi, d, -b);
+  const float s = a + b;
+  const float sv = s - a;
+  const float es = (a - (s - sv)) + (b - sv);
+  return (s + (((ea + eb) + es) + tlo * d)) * inv_h;
+}
+
 __device__ __forceinline__ f32x16 mma(s16x8 a, s16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
                                                 __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);

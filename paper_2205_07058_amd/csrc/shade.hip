@@ -162,34 +162,6 @@ struct Smem {
   }
 };
 
-// The segment midpoint t = (t0 + t1) / 2 as an unevaluated sum hi + lo
-// (TwoSum, exact), and the cell coordinate (o + t d - lo_plane) / h of the
-// point there, evaluated with error-free transformations (TwoSum, FMA
-// residual of the product): its error stays a few ulps of the result even
-// when the origin lies far from the cell, where plain binary32 evaluation
-// loses about |o| 2^-24 absolutely and 1/h (up to 2^9) scales that up.
-__device__ __forceinline__ void midpoint2(float t0, float t1, float& hi, float& lo) {
-#pragma clang fp contract(off)
-  const float s = t0 + t1;
-  const float v = s - t0;
-  const float e = (t0 - (s - v)) + (t1 - v);
-  hi = 0.5f * s;
-  lo = 0.5f * e;
-}
-__device__ __forceinline__ float cell_coord(float o, float d, float thi, float tlo, float plane,
-                                            float inv_h) {
-#pragma clang fp contract(off)
-  const float a = o - plane;
-  const float av = a - o;
-  const float ea = (o - (a - av)) + (-plane - av);
-  const float b = thi * d;
-  const float eb = __builtin_fmaf(thi, d, -b);
-  const float s = a + b;
-  const float sv = s - a;
-  const float es = (a - (s - sv)) + (b - sv);
-  return (s + (((ea + eb) + es) + tlo * d)) * inv_h;
-}
-
 template <class CF>
 __device__ __forceinline__ typename CF::Elem to_elem(float v) {
   if constexpr (CF::BF) return static_cast<uint16_t>(bf16_rne(v));

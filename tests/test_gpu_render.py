@@ -394,3 +394,20 @@ def test_depth_10_scene(gpu_lib):
     eF, ep = render_backward(st, g_rgb, g_dep)
     assert_grad_close(gF, eF, "depth 10 grad_features")
     assert_grad_close(gp, ep, "depth 10 grad_params", rel_nw=1e-4, rel_el=None)
+    # the light-field function on the same scene and rays
+    from tests.gpu_cases import LfCase
+    from oracle.lightfield import render_lf_backward
+    lf = LfCase(gpu_lib, cells, depth, rng.normal(0.0, 0.5, (nv, 96)).astype(np.float32),
+                LfCase.random(gpu_lib, 10, 5, K=8).p, 8)
+    lrgb, ldep, lacc = lf.gpu_render(o, d)
+    lr, ld, la, _ = lf.oracle(o, d)
+    assert_outputs_close(lrgb, lr, 1.0, "depth 10 lf rgb")
+    assert_outputs_close(ldep, ld, max(1.0, np.abs(ld).max()), "depth 10 lf depth")
+    keep = lf.smooth_rays(o, d)
+    lg_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)
+    lg_dep = rng.normal(size=keep.size).astype(np.float32)
+    lgF, lgp = lf.gpu_backward(o[keep], d[keep], lg_rgb, lg_dep)
+    _, _, _, lst = lf.oracle(o[keep], d[keep])
+    leF, lep = render_lf_backward(lst, lg_rgb, lg_dep)
+    assert_grad_close(lgF, leF, "depth 10 lf grad_features")
+    assert_grad_close(lgp, lep, "depth 10 lf grad_params", rel_nw=1e-4, rel_el=None)
