@@ -28,6 +28,7 @@ __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ p, float*
                                                    int64_t n, float lr, float b1, float b2,
                                                    float eps, float bc1, float bc2,
                                                    uint16_t* __restrict__ bf, int zero) {
+#pragma clang fp contract(off)   // the same rounding in every path (no fused multiply-adds)
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
     const float gi = g[i];
@@ -39,6 +40,41 @@ __global__ __launch_bounds__(kThreads) void k_adam(float* __restrict__ p, float*
     p[i] = pi;
     if (bf) bf[i] = bf16_bits(pi);
     if (zero) g[i] = 0.0f;
+  }
+}
+
+// The same update, four consecutive parameters per thread (16-byte loads
+// and stores; identical arithmetic per element).
+__global__ __launch_bounds__(kThreads) void k_adam4(float4* __restrict__ p, float4* __restrict__ g,
+                                                    float4* __restrict__ m, float4* __restrict__ v,
+                                                    int64_t n4, float lr, float b1, float b2,
+                                                    float eps, float bc1, float bc2,
+                                                    uint2* __restrict__ bf, int zero) {
+#pragma clang fp contract(off)   // the same rounding in every path (no fused multiply-adds)
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n4; i += stride) {
+    const float4 gi = g[i];
+    float4 mi = m[i], vi = v[i], pi = p[i];
+    float* mf = &mi.x;
+    float* vf = &vi.x;
+    float* pf = &pi.x;
+    const float* gf = &gi.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mf[c] = b1 * mf[c] + (1.0f - b1) * gf[c];
+      vf[c] = b2 * vf[c] + (1.0f - b2) * gf[c] * gf[c];
+      pf[c] = pf[c] - lr * (mf[c] / bc1) / (sqrtf(vf[c] / bc2) + eps);
+    }
+    m[i] = mi;
+    v[i] = vi;
+    p[i] = pi;
+    if (bf) {
+      uint2 b;
+      b.x = static_cast<uint32_t>(bf16_bits(pi.x)) | (static_cast<uint32_t>(bf16_bits(pi.y)) << 16);
+      b.y = static_cast<uint32_t>(bf16_bits(pi.z)) | (static_cast<uint32_t>(bf16_bits(pi.w)) << 16);
+      bf[i] = b;
+    }
+    if (zero) g[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 }
 
@@ -54,6 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_lazy_adam(float4* __restrict__ p,
                                                         int L4, float lr, float b1, float b2,
                                                         float eps, float bc1, float bc2,
                                                         uint2* __restrict__ bf, int zero) {
+#pragma clang fp contract(off)   // the same rounding in every path (no fused multiply-adds)
   const int lane = threadIdx.x & 63;
   const int rpw = 64 / L4;
   const int grp = lane / L4;
@@ -160,8 +197,18 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const float* __restrict__ p
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, float bc1, float bc2, uint16_t* bf16, int zero,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(kThreads), 0, s, p, g, m, v, n, lr, b1, b2,
-                     eps, bc1, bc2, bf16, zero);
+  const auto a16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+  const bool vec = n % 4 == 0 && a16(p) && a16(g) && a16(m) && a16(v) &&
+                   (bf16 == nullptr || (reinterpret_cast<uintptr_t>(bf16) & 7u) == 0);
+  if (vec) {
+    hipLaunchKernelGGL(k_adam4, dim3(grid_for(n / 4)), dim3(kThreads), 0, s,
+                       reinterpret_cast<float4*>(p), reinterpret_cast<float4*>(g),
+                       reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n / 4, lr, b1,
+                       b2, eps, bc1, bc2, reinterpret_cast<uint2*>(bf16), zero);
+  } else {
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(kThreads), 0, s, p, g, m, v, n, lr, b1, b2,
+                       eps, bc1, bc2, bf16, zero);
+  }
   return hipGetLastError();
 }
 

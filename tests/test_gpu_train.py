@@ -58,10 +58,12 @@ def test_autograd_matches_render_backward(gpu_lib):
         assert abs(fd - an) <= 2e-3 * abs(an), (fd, an)
 
 
-def test_adam_kernel(gpu_lib):
+@pytest.mark.parametrize("n", [100003, 100000])
+def test_adam_kernel(gpu_lib, n):
+    """Against torch's Adam; n = 100000 takes the four-wide path (aligned,
+    length a multiple of 4), n = 100003 the scalar one."""
     import torch
     rng = np.random.default_rng(0)
-    n = 100003
     p0 = rng.normal(size=n).astype(np.float32)
     p = _t(p0.copy())
     ref = torch.nn.Parameter(torch.from_numpy(p0.copy()).cuda())
@@ -81,6 +83,31 @@ def test_adam_kernel(gpu_lib):
     bits = bf.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     np.testing.assert_array_equal(bits.view(np.float32),
                                   p.to(torch.bfloat16).float().cpu().numpy())
+
+
+def test_adam_four_wide_matches_scalar(gpu_lib):
+    """The four-wide and the scalar Adam paths give identical bits (the same
+    arrays at offset 1 inside larger buffers are not 16-byte aligned and take
+    the scalar path)."""
+    import torch
+    rng = np.random.default_rng(3)
+    n = 4096
+    p0, m0 = rng.normal(size=n).astype(np.float32), rng.normal(size=n).astype(np.float32) * 0.1
+    v0 = np.abs(rng.normal(size=n)).astype(np.float32) * 0.01
+    g0 = rng.normal(size=n).astype(np.float32)
+    outs = []
+    for off in (0, 1):
+        bufs = [torch.zeros(n + 4, dtype=torch.float32, device="cuda") for _ in range(4)]
+        p, g, m, v = (b[off:off + n] for b in bufs)
+        for dst, src in ((p, p0), (g, g0), (m, m0), (v, v0)):
+            dst.copy_(_t(src))
+        bfb = torch.zeros(n + 4, dtype=torch.int16, device="cuda")
+        bf = bfb[off:off + n]
+        gpu_lib.adam_step(p, g, m, v, 1e-2, 0.9, 0.999, 1e-8, 3, bf16_out=bf, zero_grad=True)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy().copy() for x in (p, m, v, g, bf)])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
 @pytest.mark.parametrize("row_len", [32, 12, 256])
