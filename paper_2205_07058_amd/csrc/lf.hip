@@ -388,7 +388,7 @@ struct DCfg {
   static constexpr int LDS = L_SCR + 64;
   static_assert(LDS <= 160 * 1024, "LDS");
   static_assert(!BWD || WIN * 2 * kLfCT * 4 <= L_MAP - L_GZ, "dL/dz staging fits in GZ + AT");
-  static_assert(M::NBIAS <= kThreads, "bias gradients owned one per thread");
+  static_assert(M::NBIAS <= kThreads, "one thread per bias entry writes its combined gradient");
 };
 
 // Bias gradients of layer l (ROWS real rows of width RW in GZ, one column

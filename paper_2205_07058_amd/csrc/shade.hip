@@ -20,7 +20,10 @@
 //  * backward: dL/dz of each layer and the layer's input are written to LDS
 //    transposed ([feature][hit]) and every wave accumulates the dW tiles it
 //    owns over all windows in registers (K = hits); the data gradient uses a
-//    second, transposed weight pack.
+//    second, transposed weight pack;
+//  * backward: a window's feature-gradient atomics are issued after the next
+//    window's gather, and the next window's hit records and corner ids are
+//    loaded while the current window computes (the window loop).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -119,7 +122,7 @@ struct Cfg {
   static constexpr int L_MAP2 = align16(L_REC2 + (BWD ? WIN * 64 : 0));
   static constexpr int L_SCR = align16(L_MAP2 + (BWD ? WIN * 4 : 0));
   static constexpr int LDS_BYTES = L_SCR + 64;
-  static_assert(NBIAS <= kThreads, "bias gradients are owned one per thread");
+  static_assert(NBIAS <= kThreads, "one thread per bias entry writes its combined gradient");
   static_assert(C <= 32 && CI <= TROWS, "feature gradients come from one 32-row tile");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
   static_assert(!BWD || WIN * C * 4 <= 2 * TROWS * TS * EB, "dL/dx staging fits in GZ + AT");
