@@ -239,8 +239,9 @@ __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ 
         }
       }
     }
-    if (rem == 0) {
-      if (level == 0) break;
+    // back up to the nearest level with a sibling left, then descend into it
+    // in the same iteration
+    while (rem == 0 && level > 0) {
       --level;
       ci >>= 1;
       cj >>= 1;
@@ -249,8 +250,8 @@ __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ 
       nd.child = static_cast<int32_t>(e.x);
       nd.mask = e.y & 0xFFu;
       rem = e.y >> 8;
-      continue;
     }
+    if (rem == 0) break;
     const uint32_t i = __builtin_ctz(rem);
     rem &= rem - 1;
     const uint32_t c = i ^ r.oct;
