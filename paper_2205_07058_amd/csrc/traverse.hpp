@@ -217,10 +217,8 @@ __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ 
   uint32_t ci = 0, cj = 0, ck = 0;   // mirrored cell coordinates
   svlf_node nd = load_node(nrs, 0);
   uint32_t rem = 0;
-  bool expand = true;
   while (true) {
-    if (expand) {
-      expand = false;
+    {
       const Kids kd = node_kids<PAR>(r, level, ci, cj, ck);
       rem = kid_hits(kd) & mirror_mask(nd.mask, r.oct);
       if (level == depth - 1) {
@@ -262,7 +260,6 @@ __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ 
     cj = 2 * cj + ((i >> 1) & 1);
     ck = 2 * ck + (i >> 2);
     nd = load_node(nrs, idx);
-    expand = true;
   }
   return count;
 }
