@@ -40,6 +40,7 @@ namespace {
 using namespace detail;
 
 constexpr int kThreads = 256;
+static_assert(kThreads == kRaysPerBlock, "one ray per thread in a work item");
 constexpr int kWaves = 4;
 
 // ------------------------------------------------------------ decoder geometry
@@ -478,8 +479,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
   const int lb = (G % 8 == 0) ? (bidx % 8) * (G / 8) + bidx / 8 : bidx;
   for (int item = lb; item < a.tab.n_blocks; item += G) {
     const DevScene& sc = a.tab.s[scene_of(a.tab, item)];
-    const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
-    const int64_t r = ray0 + tid;
+    const ItemRays ir = item_rays(sc, item);
+    const int64_t r = ir.ray(tid);
     const int count = r < sc.ray_end ? a.cnt[r] : 0;
     const float h = __int_as_float((128 - sc.depth) << 23);
     const float inv_h = __int_as_float((126 + sc.depth) << 23);
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
         for (int hh = tid; hh < CF::WIN; hh += kThreads) {
           if (hh < tw) {
             const int mp = hmap[hh];
-            const int64_t ray = ray0 + (mp & 0xFFFF);
+            const int64_t ray = ir.ray(mp & 0xFFFF);
             const HitRec hr = a.hits[ray * a.K + (mp >> 16)];
             const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
             const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           uint4 v = make_uint4(0u, 0u, 0u, 0u);
           if (hh < tw) {
             const int mp = hmap[hh];
-            const int64_t slot = (ray0 + (mp & 0xFFFF)) * a.K + (mp >> 16);
+            const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
             v = *reinterpret_cast<const uint4*>(a.xsave + slot * M::IN0P + 8 * c);
           }
           *reinterpret_cast<uint4*>(dX<CF>() + hh * CF::XS + 8 * c) = v;
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           float rr[6] = {0, 0, 0, 0, 0, 0};
           if (hh < tw) {
             const int mp = hmap[hh];
-            const int64_t ray = ray0 + (mp & 0xFFFF);
+            const int64_t ray = ir.ray(mp & 0xFFFF);
             const HitRec hr = a.hits[ray * a.K + (mp >> 16)];
             const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
             const float dx = a.d[3 * ray], dy = a.d[3 * ray + 1], dz = a.d[3 * ray + 2];
@@ -618,7 +619,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
         for (int e = tid; e < tw * CPR; e += kThreads) {
           const int hh = e / CPR, c = e % CPR;
           const int mp = hmap[hh];
-          const int64_t slot = (ray0 + (mp & 0xFFFF)) * a.K + (mp >> 16);
+          const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
           *reinterpret_cast<uint4*>(a.xsave + slot * M::IN0P + 8 * c) =
               *reinterpret_cast<const uint4*>(dX<CF>() + hh * CF::XS + 8 * c);
         }
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           const int hh = n0 + lane;
           const DRec rc = rec[hh];
           const int mp = hmap[hh];
-          const int64_t slot = (ray0 + (mp & 0xFFFF)) * a.K + (mp >> 16);
+          const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
           const float dt = rc.tout - rc.tin;
           const float ft = a.tau_mode == SVLF_TAU_VOXEL ? dt * inv_h
                            : a.tau_mode == SVLF_TAU_WORLD ? dt : 1.0f;
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
         for (int mt = 0; mt < M::MTH; ++mt) gz[mt] = zero16();
         if (has_tile && g == 0 && n0 + lane < tw) {
           const int mp = hmap[n0 + lane];
-          const int64_t slot = (ray0 + (mp & 0xFFFF)) * a.K + (mp >> 16);
+          const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
           const float2 gv = *reinterpret_cast<const float2*>(a.gT + 2 * slot);
           gz[0][0] = gv.x;
           gz[0][1] = gv.y;
@@ -879,8 +880,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
     const float* featC32 = sc.feat32 + zc;
     const uint16_t* featC16 = sc.feat16 != nullptr ? sc.feat16 + zc : nullptr;
     float* gradC = sc.grad != nullptr ? sc.grad + zc : nullptr;
-    const int64_t ray0 = sc.ray_begin + static_cast<int64_t>(item - sc.block_begin) * kThreads;
-    const int64_t r = ray0 + tid;
+    const ItemRays ir = item_rays(sc, item);
+    const int64_t r = ir.ray(tid);
     const bool live = r < sc.ray_end;
     const int count = live ? a.cnt[r] : 0;
     const float h = __int_as_float((128 - sc.depth) << 23);
@@ -905,7 +906,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
           float rr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
           if (hh < tw) {
             const int mp = hmap[hh];
-            const int64_t ray = ray0 + (mp & 0xFFFF);
+            const int64_t ray = ir.ray(mp & 0xFFFF);
             const int64_t slot = ray * a.K + (mp >> 16);
             const HitRec hr = a.hits[slot];
             const LfHit st = a.st[slot];
@@ -1298,7 +1299,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
                   gu[ax] += dwv * proj[j];
                 }
               }
-              const int64_t ray = ray0 + rc.ray_lane;
+              const int64_t ray = ir.ray(rc.ray_lane);
               const float dir[3] = {a.d[3 * ray], a.d[3 * ray + 1], a.d[3 * ray + 2]};
               float gx_d = 0.0f;
 #pragma unroll

@@ -24,11 +24,8 @@
 //  * backward: a window's feature-gradient atomics are issued after the next
 //    window's gather, and the next window's hit records and corner ids are
 //    loaded while the current window computes (the window loop);
-//  * backward: the rays of kIlv consecutive full work items are interleaved
-//    (item j of the group takes rays j, j + kIlv, j + 2 kIlv, ... of the
-//    group), so that one item's rays lie far apart in the caller's ray order
-//    while the group, whose items run at about the same time, still covers
-//    one contiguous range of rays.
+//  * the rays of groups of consecutive full work items are interleaved
+//    (item_rays), which shortened both the train and the forward pass.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -43,7 +40,7 @@ namespace {
 using namespace detail;
 
 constexpr int kThreads = 256;
-constexpr int kIlv = 256;   // work items per interleaved group (backward)
+static_assert(kThreads == kRaysPerBlock, "one ray per thread in a work item");
 constexpr int kWaves = 4;
 
 // ------------------------------------------------------------ geometry
@@ -446,12 +443,8 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     int si = 0;
     while (si + 1 < a.tab.n && item >= a.tab.s[si + 1].block_begin) ++si;
     const DevScene& sc = a.tab.s[si];
-    // ray of lane t: rbase + t * rstride (interleaved groups: see the top)
-    const int64_t li = item - sc.block_begin, g0 = li / kIlv * kIlv;
-    const bool ilv = CF::BWD && (g0 + kIlv) * kThreads <= sc.ray_end - sc.ray_begin;
-    const int64_t rbase = sc.ray_begin + (ilv ? g0 * kThreads + (li - g0) : li * kThreads);
-    const int rstride = ilv ? kIlv : 1;
-    const int64_t r = rbase + static_cast<int64_t>(tid) * rstride;
+    const ItemRays ir = item_rays(sc, item);
+    const int64_t r = ir.ray(tid);
     const bool live = r < sc.ray_end;
     const int count = live ? a.cnt[r] : 0;
     // the ray's target (train) or upstream gradient (backward), read before
@@ -516,7 +509,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         st.val[k] = st.hh[k] < twin;
         if (st.val[k]) {
           const int mp = sm.hmap(hb)[st.hh[k]];
-          const int64_t rr = rbase + static_cast<int64_t>(mp & 0xFFFF) * rstride;
+          const int64_t rr = ir.ray(mp & 0xFFFF);
           st.hr[k] = a.hits[rr * a.K + (mp >> 16)];
           st.ro[k][0] = a.o[3 * rr]; st.ro[k][1] = a.o[3 * rr + 1]; st.ro[k][2] = a.o[3 * rr + 2];
           st.rd[k][0] = a.d[3 * rr]; st.rd[k][1] = a.d[3 * rr + 1]; st.rd[k][2] = a.d[3 * rr + 2];
@@ -855,7 +848,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
                 const RecL rc = sm.rec(rb)[hh];
                 const int mp = sm.hmap(hb)[hh];
                 const int64_t slot =
-                    (rbase + static_cast<int64_t>(mp & 0xFFFF) * rstride) * a.K + (mp >> 16);
+                    ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
                 float* rec_out = a.gxu + slot * (CF::C + 4);
                 rec_out[4 + c] = gxs[hh * CF::C + c];
                 if (c < 3) rec_out[c] = c == 0 ? rc.ux : (c == 1 ? rc.uy : rc.uz);

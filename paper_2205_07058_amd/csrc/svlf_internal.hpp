@@ -47,6 +47,31 @@ struct HitRec {
 
 constexpr int kRaysPerBlock = 256;
 
+// Rays of one work item (kRaysPerBlock rays) of the shading kernels.  The
+// rays of kIlvItems consecutive full items of a scene are interleaved: item
+// j of such a group takes rays j, j + kIlvItems, j + 2 kIlvItems, ... of
+// the group, so that one item's rays lie far apart in the caller's order
+// while the group, whose items run at about the same time, covers one
+// contiguous range.  Other items take kRaysPerBlock consecutive rays.
+// Lane t of the item handles ray base + t * stride (it may be past the
+// scene's last ray only in a scene's last, partial item).
+constexpr int kIlvItems = 256;
+
+struct ItemRays {
+  int64_t base;
+  int stride;
+  __device__ __forceinline__ int64_t ray(int lane) const {
+    return base + static_cast<int64_t>(lane) * stride;
+  }
+};
+
+__device__ __forceinline__ ItemRays item_rays(const DevScene& sc, int item) {
+  const int64_t li = item - sc.block_begin, g0 = li / kIlvItems * kIlvItems;
+  if ((g0 + kIlvItems) * kRaysPerBlock <= sc.ray_end - sc.ray_begin)
+    return {sc.ray_begin + g0 * kRaysPerBlock + (li - g0), kIlvItems};
+  return {sc.ray_begin + li * kRaysPerBlock, 1};
+}
+
 // Launchers (defined in the .hip files).
 hipError_t launch_trace_public(const svlf_octree& oct, const float* o, const float* d,
                                int64_t n, int K, int32_t* leaf, float* tin, float* tout,

@@ -18,11 +18,12 @@ class Trainer:
     def __init__(self, scene: "svlf.DeviceScene", params: torch.Tensor, widths, K,
                  precision="bf16", tau_mode="voxel", lr_features=1e-3, lr_params=1e-3,
                  lambda_depth=0.1, betas=(0.9, 0.999), eps=1e-8, feature_optimizer="adam",
-                 viewdir=False):
+                 viewdir=False, deterministic=False):
         self.scene = scene
         self.params = params
         self.widths = tuple(widths)
-        self.opts = svlf.make_opts(K, tau_mode, precision, svlf.FLAG_VIEWDIR if viewdir else 0)
+        flags = (svlf.FLAG_VIEWDIR if viewdir else 0) | (svlf.FLAG_DETERMINISTIC if deterministic else 0)
+        self.opts = svlf.make_opts(K, tau_mode, precision, flags)
         self.precision = precision
         self.lr_f, self.lr_p = lr_features, lr_params
         self.lam = lambda_depth

@@ -173,7 +173,7 @@ def test_deterministic_train_step_paper_scale(gpu_lib, paper):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_train_step_full_batch_equals_chunked_calls(gpu_lib, paper, precision):
-    """The backward kernels interleave the rays of groups of 256 full work
+    """The shading kernels interleave the rays of groups of 256 full work
     items (65,536 rays); calls of 60,000 rays have no full group and take
     the rays in order.  The full-batch train step must give the same per-ray
     outputs (bit-exact: each ray is composited on its own), the same loss
@@ -211,4 +211,49 @@ def test_train_step_full_batch_equals_chunked_calls(gpu_lib, paper, precision):
     assert abs(La - Lb) <= 1e-5 * abs(Lb)
     sf, sp = np.abs(fb).max(), np.abs(pb).max()
     assert sf > 0 and np.abs(fa - fb).max() <= 1e-5 * sf
+    assert sp > 0 and np.abs(pa - pb).max() <= 1e-4 * sp
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_lightfield_train_step_full_batch_equals_chunked_calls(gpu_lib, paper, precision):
+    """As for the single decoder: the light-field kernels interleave the rays
+    of full 65,536-ray groups, so the full-batch train step must match the
+    sum of 60,000-ray calls (per-ray outputs bit-exact, loss and gradients up
+    to FP32 summation order)."""
+    import torch
+    from synth.configs import lf_inputs
+    w, sc = paper["w"], paper["sc"]
+    F, p = lf_inputs(w.seed, sc.n_vertices)
+    scene = gpu_lib.DeviceScene.lf_from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    params = torch.from_numpy(p).cuda()
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
+    n = ob.shape[0]
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    o, d, tr, td = T(ob), T(db), T(rgb_t), T(dep_t)
+    opts = gpu_lib.make_opts(w.K, "direct", precision)
+
+    def run(bounds):
+        gF = torch.zeros_like(scene.features)
+        gp = torch.zeros_like(params)
+        rgb = torch.empty((n, 3), device="cuda")
+        dep = torch.empty(n, device="cuda")
+        L = 0.0
+        for lo, hi in zip(bounds[:-1], bounds[1:]):
+            gpc = torch.zeros_like(gp)
+            loss = torch.zeros(1, device="cuda")
+            gpu_lib.lf_train_step([scene], [hi - lo], params, opts, o[lo:hi], d[lo:hi], tr[lo:hi],
+                                  td[lo:hi], 0.1, 1.0 / n, [gF], gpc, out_rgb=rgb[lo:hi],
+                                  out_depth=dep[lo:hi], loss_out=loss)
+            gp += gpc
+            L += float(loss.item())
+        torch.cuda.synchronize()
+        return gF.cpu().numpy(), gp.cpu().numpy(), rgb.cpu().numpy(), dep.cpu().numpy(), L
+
+    fa, pa, ra, da, La = run([0, n])
+    fb, pb, rb, db_, Lb = run(list(range(0, n, 60000)) + [n])
+    assert np.array_equal(ra.view(np.int32), rb.view(np.int32))
+    assert np.array_equal(da.view(np.int32), db_.view(np.int32))
+    assert abs(La - Lb) <= 1e-5 * abs(Lb)
+    sf, sp = np.abs(fb).max(), np.abs(pb).max()
+    assert sf > 0 and np.abs(fa - fb).max() <= 1e-4 * sf
     assert sp > 0 and np.abs(pa - pb).max() <= 1e-4 * sp

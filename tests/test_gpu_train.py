@@ -266,7 +266,8 @@ def test_checkpoint_resume(gpu_lib):
 
     def fresh():
         return Trainer(gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features()),
-                       _t(w.params().copy()), w.widths, w.K, precision="bf16", lr_features=1e-2)
+                       _t(w.params().copy()), w.widths, w.K, precision="bf16", lr_features=1e-2,
+                       deterministic=True)
 
     batches = [w.train_batch(4096, step=i) for i in range(20)]
     a = fresh()
@@ -281,7 +282,9 @@ def test_checkpoint_resume(gpu_lib):
     for o, d, rgb, dep in batches[10:]:
         c.step(_t(o), _t(d), _t(rgb), _t(dep))
     torch.cuda.synchronize()
-    # FP32 atomics make runs differ in the last bits only
-    np.testing.assert_allclose(c.params.cpu().numpy(), a.params.cpu().numpy(), rtol=1e-3, atol=1e-5)
-    np.testing.assert_allclose(c.scene.features.cpu().numpy(), a.scene.features.cpu().numpy(),
-                               rtol=1e-3, atol=1e-5)
+    # with the deterministic feature-gradient reduction (and the decoder
+    # gradient summed in a fixed order) training is reproducible bit for bit;
+    # with FP32 atomics Adam turns last-bit gradient differences of
+    # near-zero entries into visible steps
+    assert torch.equal(c.params, a.params)
+    assert torch.equal(c.scene.features, a.scene.features)
