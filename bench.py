@@ -38,15 +38,19 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the BF16 train shading kernel on this workload,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 1 GiB device copy
 # (profiles/shade_train_bf16_paper_scale.md).  Valid only for the kernel
-# source they were taken with; reported as null once shade.hip changes.
+# sources they were taken with (shade.hip and the two headers it includes);
+# reported as null once any of them changes.
 MEASURED_TRAFFIC = {"shade_src_sha256_prefix": "db71792ab17aa36a", "bytes": 2 * 426512 * 1024 + 1424027 * 1024}
+SHADE_SOURCES = ("shade.hip", "mfma_common.hpp", "svlf_internal.hpp")
 
 
 def shade_source_prefix():
     import hashlib
-    path = os.path.join(ROOT, "paper_2205_07058_amd", "csrc", "shade.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in SHADE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2205_07058_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def bench_lightfield(torch, svlf, timer, args, w, sc, ob_t, db_t, rgb_tt, dep_tt, ov_t, dv_t,
