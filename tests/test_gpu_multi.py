@@ -107,3 +107,59 @@ def test_multi_scene_graph_replay(gpu_lib):
         for gg, rr in zip(got[3:], ref[3:]):
             np.testing.assert_allclose(gg.cpu().numpy(), rr.cpu().numpy(), rtol=1e-4,
                                        atol=1e-6 * float(rr.abs().max()) + 1e-30)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_multi_scene_interleaved_groups_match_per_scene_calls(gpu_lib, precision):
+    """Scenes with full 65,536-ray groups (whose rays the shading kernels
+    interleave), exact and ragged multiples and a small scene after them, in
+    one call: per-ray outputs bit-exact and gradients (up to FP32 summation
+    order) equal to calls made scene by scene."""
+    import torch
+    m = get_multi(small=True)
+    p = m.params()
+    p[-1] = 0.6
+    counts = [70000, 65536, 131149, 513]
+    cases, os_, ds_ = [], [], []
+    for i, n_i in enumerate(counts):
+        sc = m.scene(5 + i % 3)
+        rng = np.random.default_rng(200 + i)
+        F = rng.normal(0, 0.4, (sc.n_vertices, m.C)).astype(np.float32)
+        cases.append(Case(gpu_lib, sc.leaf_ijk, sc.depth, F, p, m.widths, m.K))
+        o, d = m.rays(5 + i % 3, n_i)
+        os_.append(o)
+        ds_.append(d)
+    o, d = np.concatenate(os_), np.concatenate(ds_)
+    n = o.shape[0]
+    to, td = cases[0].rays(o, d)
+    rng = np.random.default_rng(1)
+    t_rgb = torch.from_numpy(rng.uniform(0, 1, (n, 3)).astype(np.float32)).cuda()
+    t_dep = torch.from_numpy(rng.uniform(0, 6, n).astype(np.float32)).cuda()
+    params = cases[0].params
+    opts = cases[0].opts(precision)
+
+    def run(groups):
+        gFs = [torch.zeros_like(c.scene.features) for c in cases]
+        gp = torch.zeros_like(params)
+        rgb = torch.empty((n, 3), device="cuda")
+        dep = torch.empty(n, device="cuda")
+        for ids in groups:
+            lo = sum(counts[:ids[0]])
+            hi = lo + sum(counts[i] for i in ids)
+            gpc = torch.zeros_like(gp)
+            gpu_lib.train_step([cases[i].scene for i in ids], [counts[i] for i in ids], params, m.widths,
+                               opts, to[lo:hi], td[lo:hi], t_rgb[lo:hi], t_dep[lo:hi], 0.1, 1.0 / n,
+                               [gFs[i] for i in ids], gpc, out_rgb=rgb[lo:hi], out_depth=dep[lo:hi])
+            gp += gpc
+        torch.cuda.synchronize()
+        return [g.cpu().numpy() for g in gFs], gp.cpu().numpy(), rgb.cpu().numpy(), dep.cpu().numpy()
+
+    fa, pa, ra, da = run([list(range(len(counts)))])
+    fb, pb, rb, db = run([[i] for i in range(len(counts))])
+    assert np.array_equal(ra.view(np.int32), rb.view(np.int32))
+    assert np.array_equal(da.view(np.int32), db.view(np.int32))
+    for k, (ga, gb) in enumerate(zip(fa, fb)):
+        s = np.abs(gb).max()
+        assert (s > 0 or counts[k] < 65536) and np.abs(ga - gb).max() <= 1e-5 * s
+    sp = np.abs(pb).max()
+    assert sp > 0 and np.abs(pa - pb).max() <= 1e-4 * sp
