@@ -22,13 +22,16 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_public(
     int32_t* __restrict__ leaf_out, float* __restrict__ tin_out, float* __restrict__ tout_out,
     int32_t* __restrict__ cnt_out) {
   extern __shared__ uint2 stk[];
+  __shared__ uint8_t mtab[kMirrorTableBytes];
+  fill_mirror_table(mtab, threadIdx.x, kTraceThreads);
+  __syncthreads();
   const int64_t r = static_cast<int64_t>(blockIdx.x) * kTraceThreads + threadIdx.x;
   if (r >= n) return;
   int count = 0;
   const int64_t base = r * K;
   if (n_leaves > 0) {
     const Ray ray = load_ray(o, d, r);
-    count = traverse(ray, nodes, depth, K, stk + threadIdx.x, kTraceThreads,
+    count = traverse(ray, nodes, depth, K, stk + threadIdx.x, kTraceThreads, mtab,
                      [&](int slot, int32_t leaf, float t0, float t1, uint32_t) {
                        leaf_out[base + slot] = leaf;
                        tin_out[base + slot] = t0;
@@ -49,6 +52,9 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_internal(
     SceneTable tab, const float* __restrict__ o, const float* __restrict__ d, int K,
     HitRec* __restrict__ hits, int32_t* __restrict__ cnt_out) {
   extern __shared__ uint2 stk[];
+  __shared__ uint8_t mtab[kMirrorTableBytes];
+  fill_mirror_table(mtab, threadIdx.x, kTraceThreads);
+  __syncthreads();
   const int b = blockIdx.x;
   int s = 0;
   while (s + 1 < tab.n && b >= tab.s[s + 1].block_begin) ++s;
@@ -60,7 +66,7 @@ __global__ __launch_bounds__(kTraceThreads) void k_trace_internal(
   if (sc.nodes != nullptr) {
     const Ray ray = load_ray(o, d, r);
     HitRec* out = hits + r * K;
-    count = traverse(ray, sc.nodes, sc.depth, K, stk + threadIdx.x, kTraceThreads,
+    count = traverse(ray, sc.nodes, sc.depth, K, stk + threadIdx.x, kTraceThreads, mtab,
                      [&](int slot, int32_t leaf, float t0, float t1, uint32_t ijk) {
                        HitRec h;
                        h.leaf = leaf;

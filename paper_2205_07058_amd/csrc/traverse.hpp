@@ -165,6 +165,16 @@ __device__ __forceinline__ uint32_t mirror_mask(uint32_t m, uint32_t oct) {
   return m;
 }
 
+// mirror_mask for every (oct, m) as a byte table, entry (oct << 8) | m:
+// the kernels keep it in LDS, where one lookup replaces the three
+// conditional bit swaps in the walk's loop.
+constexpr int kMirrorTableBytes = 8 * 256;
+
+__device__ __forceinline__ void fill_mirror_table(uint8_t* t, int tid, int nthreads) {
+  for (int e = tid; e < kMirrorTableBytes; e += nthreads)
+    t[e] = static_cast<uint8_t>(mirror_mask(static_cast<uint32_t>(e) & 0xFFu, static_cast<uint32_t>(e) >> 8));
+}
+
 // Root cell [-1, 1]^3 test (the cell is its own mirror image).
 __device__ __forceinline__ bool root_hit(const Ray& r) {
 #pragma clang fp contract(off)
@@ -204,7 +214,7 @@ __device__ __forceinline__ svlf_node load_node(__amdgpu_buffer_rsrc_t rs, int32_
 
 template <bool PAR, class Emit>
 __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ nodes, int depth,
-                                    int K, uint2* stk, int stride, Emit emit) {
+                                    int K, uint2* stk, int stride, const uint8_t* mtab, Emit emit) {
   // node indices are < 2^28, so byte offsets fit the 32-bit buffer range
   const __amdgpu_buffer_rsrc_t nrs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<svlf_node*>(nodes), 0, 0x7FFFFFFF, 0x00020000);
@@ -220,7 +230,7 @@ __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ 
   while (true) {
     {
       const Kids kd = node_kids<PAR>(r, level, ci, cj, ck);
-      rem = kid_hits(kd) & mirror_mask(nd.mask, r.oct);
+      rem = kid_hits(kd) & mtab[(r.oct << 8) | (nd.mask & 0xFFu)];
       if (level == depth - 1) {
         // children are leaves: emit them in order
         while (rem) {
@@ -272,10 +282,11 @@ __device__ __forceinline__ int walk(const Ray& r, const svlf_node* __restrict__ 
 // no code for them.
 template <class Emit>
 __device__ __forceinline__ int traverse(const Ray& r, const svlf_node* __restrict__ nodes,
-                                        int depth, int K, uint2* stk, int stride, Emit emit) {
+                                        int depth, int K, uint2* stk, int stride,
+                                        const uint8_t* mtab, Emit emit) {
   if (!r.valid || !root_hit(r)) return 0;
-  if (r.nonfin) return walk<true>(r, nodes, depth, K, stk, stride, emit);
-  return walk<false>(r, nodes, depth, K, stk, stride, emit);
+  if (r.nonfin) return walk<true>(r, nodes, depth, K, stk, stride, mtab, emit);
+  return walk<false>(r, nodes, depth, K, stk, stride, mtab, emit);
 }
 
 }  // namespace svlf
