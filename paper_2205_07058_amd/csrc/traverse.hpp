@@ -146,12 +146,17 @@ __device__ __forceinline__ uint32_t kid_hits(const Kids& k) {
   uint32_t m = 0;
 #pragma unroll
   for (uint32_t i = 0; i < 8; ++i) {
-    const float tn = __builtin_fmaxf(__builtin_fmaxf((i & 1) ? k.x.p1 : k.x.p0,
-                                                     (i & 2) ? k.y.p1 : k.y.p0),
-                                     (i & 4) ? z1 : z0);
-    const float tf = __builtin_fminf(__builtin_fminf((i & 1) ? k.x.p2 : k.x.p1,
-                                                     (i & 2) ? k.y.p2 : k.y.p1),
-                                     (i & 4) ? k.z.p2 : k.z.p1);
+    const float xn = (i & 1) ? k.x.p1 : k.x.p0, xf = (i & 1) ? k.x.p2 : k.x.p1;
+    const float yn = (i & 2) ? k.y.p1 : k.y.p0, yf = (i & 2) ? k.y.p2 : k.y.p1;
+    const float zn = (i & 4) ? z1 : z0, zf = (i & 4) ? k.z.p2 : k.z.p1;
+    // Children of odd index pair x with z first, the others x with y: no
+    // two children then share an inner max / min, so each folds into one
+    // three-operand max / min (the values are NaN-free, order is immaterial).
+    const bool odd = (__builtin_popcount(i) & 1) != 0;
+    const float tn = odd ? __builtin_fmaxf(__builtin_fmaxf(xn, zn), yn)
+                         : __builtin_fmaxf(__builtin_fmaxf(xn, yn), zn);
+    const float tf = odd ? __builtin_fminf(__builtin_fminf(xf, zf), yf)
+                         : __builtin_fminf(__builtin_fminf(xf, yf), zf);
     m |= (tn < tf ? 1u : 0u) << i;
   }
   return m;
