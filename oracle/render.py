@@ -211,6 +211,62 @@ def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
     return grad_F, grad_params
 
 
+def render_backward_magnitude(st, mag_rgb, mag_depth, mag_acc=None):
+    """Magnitude of the terms that make up every entry of ``render_backward``.
+
+    The backward of Eq. 3 and of the decoder is a chain of sums: the
+    compositing gradient of a segment, dL/dtau_i = sum over channels of
+    g (T_{i+1} c_i - sum_{j>i} w_j c_j), each layer's W^T dL/dz, each
+    weight gradient's sum over hits, and the trilinear scatter into a vertex
+    row.  Here every such sum is replaced by the sum of the absolute values
+    of its terms (|W| for W, T_{i+1} c_i + S_i for the difference, and so
+    on), starting from upstream magnitudes mag_* >= |dL/d output|.  Each
+    entry of the result is therefore an upper bound of the matching
+    |gradient| (triangle inequality), with equality when no sum in the chain
+    mixes signs, and it is the scale relative to which a floating-point
+    evaluation of that entry rounds: its rounding error is at most a small
+    multiple of the unit roundoff times this magnitude, however much the
+    terms cancel.  Returns (M_features (n_vertices, C), M_params)."""
+    n, K = st.n, st.K
+    m_rgb = np.abs(np.asarray(mag_rgb, np.float64)).reshape(n, 3)
+    m_d = np.abs(np.asarray(mag_depth, np.float64)).reshape(n)
+    m_a = np.zeros(n) if mag_acc is None else np.abs(np.asarray(mag_acc, np.float64)).reshape(n)
+    T, w, tau, col, tmid = st.T, st.w, st.tau, st.col, st.tmid
+    T_next = T * np.exp(-tau)
+    # the suffix sums S_i are sums of non-negative terms
+    wc = w[:, :, None] * col
+    S_c = np.sum(wc, axis=1, keepdims=True) - np.cumsum(wc, axis=1)
+    wt = w * tmid
+    S_t = np.sum(wt, axis=1, keepdims=True) - np.cumsum(wt, axis=1)
+    S_a = np.sum(w, axis=1, keepdims=True) - np.cumsum(w, axis=1)
+    m_tau = (np.sum(m_rgb[:, None, :] * (T_next[:, :, None] * col + np.abs(S_c)), axis=2)
+             + m_d[:, None] * (T_next * np.abs(tmid) + np.abs(S_t))
+             + m_a[:, None] * (T_next + np.abs(S_a)))
+    ri, si = st.ray_i, st.slot_i
+    m_out = np.zeros_like(st.out)
+    m_out[:, 3] = np.where(st.out[:, 3] > 0.0, m_tau[ri, si] * np.abs(st.dtau), 0.0)
+    c = st.c
+    m_out[:, :3] = (w[:, :, None] * m_rgb[:, None, :])[ri, si] * c * (1.0 - c)
+    layers = split_params(st.params, st.widths)
+    r = bf16_round if st.bf16 else (lambda v: v)
+    mags = []
+    m_z = m_out
+    for li in range(len(layers) - 1, -1, -1):
+        W, _ = layers[li]
+        a = np.abs(st.acts[li])
+        mags.append((m_z.T @ a, np.sum(m_z, axis=0)))
+        m_a_in = m_z @ np.abs(r(W))
+        if li > 0:
+            m_z = np.where(st.pres[li - 1] > 0.0, m_a_in, 0.0)
+        else:
+            m_X = m_a_in[:, :st.C]
+    mags.reverse()
+    m_params = np.concatenate([np.concatenate([mW.ravel(), mb]) for mW, mb in mags])
+    m_F = np.zeros((st.n_vertices, st.C))
+    np.add.at(m_F, st.corners.ravel(), (st.wj[:, :, None] * m_X[:, None, :]).reshape(-1, st.C))
+    return m_F, m_params
+
+
 def loss(rgb, depth, rgb_t, depth_t, lam_depth=0.1):
     """L = mean over rays and channels of (rgb - rgb*)^2
          + lam * mean over rays of |depth - depth*|; returns (L, dL/drgb,

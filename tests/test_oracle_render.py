@@ -16,7 +16,7 @@ import pytest
 
 from oracle.octree import Octree
 from oracle.render import (bf16_round, interpolation_weights, loss, mlp_forward,
-                           render, render_backward, split_params)
+                           render, render_backward, render_backward_magnitude, split_params)
 from oracle.trace import trace_hits
 from synth.configs import param_count, tiny_workload, xavier_params
 from tests.helpers import crafted_occupancy, random_rays
@@ -358,6 +358,99 @@ def test_acc_gradient_and_conservation():
                + g_dep @ render(oc, F * (1 - e), p, widths, o, d, hits)[1])
     fd = (Lp - Lm) / (2 * e)
     assert abs(fd - float(np.sum(gF * F))) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_gradient_magnitude_bounds_every_entry():
+    """The term magnitudes of the backward bound every gradient entry
+    (triangle inequality), also where the terms cancel, and scale linearly
+    with the upstream magnitudes."""
+    oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
+    rng = np.random.default_rng(3)
+    g_rgb = rng.normal(size=rgb.shape)
+    g_dep = rng.normal(size=dep.shape)
+    g_acc = rng.normal(size=acc.shape)
+    gF, gp = render_backward(st, g_rgb, g_dep, g_acc)
+    mF, mp = render_backward_magnitude(st, np.abs(g_rgb), np.abs(g_dep), np.abs(g_acc))
+    assert np.all(mF >= np.abs(gF) * (1 - 1e-12)) and np.all(mp >= np.abs(gp) * (1 - 1e-12))
+    # the terms do cancel on this scene (several hits per ray, mixed signs)
+    assert np.median((np.abs(gF) / np.maximum(mF, 1e-300))[mF > 0]) < 0.9
+    mF2, mp2 = render_backward_magnitude(st, 2 * np.abs(g_rgb), 2 * np.abs(g_dep), 2 * np.abs(g_acc))
+    np.testing.assert_allclose(mF2, 2 * mF, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(mp2, 2 * mp, rtol=1e-14, atol=0)
+    # each upstream output alone, on a near-opaque decoder: the later
+    # segments' share of the colour (the suffix sums) then dominates the
+    # compositing gradient of the first segments
+    p = p.copy()
+    p[-1] = 3.0
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
+    for which in range(3):
+        ups = [np.zeros_like(rgb), np.zeros_like(dep), np.zeros_like(acc)]
+        ups[which] = rng.normal(size=ups[which].shape)
+        gF, gp = render_backward(st, *ups)
+        mF, mp = render_backward_magnitude(st, *[np.abs(u) for u in ups])
+        assert np.all(mF >= np.abs(gF) * (1 - 1e-12)) and np.all(mp >= np.abs(gp) * (1 - 1e-12)), which
+
+
+def test_gradient_magnitude_dark_voxel_before_bright_one():
+    """Two leaves along a ray, a dark nearly transparent voxel in front of a
+    bright dense one: the gradient of the first voxel's optical thickness is
+    almost entirely the later voxel's share (the suffix sum of Eq. 3's
+    backward), so a magnitude without that share would fall below the
+    gradient of the first leaf's own corner features."""
+    oc = Octree([[0, 0, 0], [1, 0, 0]], 1)
+    C = 4
+    widths = (C, 4, 4)
+    p = np.zeros(param_count(widths))
+    W = split_params(p, widths)
+    W[0][0][:] = np.eye(4)
+    W[0][1][0] = 10.0             # h_0 = relu(x_0 + 10)
+    W[1][0][0, 0] = 1.0           # o_0 = h_0 - 10: colour follows x_0
+    W[1][1][0] = -10.0
+    W[1][0][3, 0] = 0.2           # sigma = relu(0.2 h_0 - 0.5)
+    W[1][1][3] = -0.5
+    F = np.zeros((oc.n_vertices, C))
+    F[:, 0] = 10.0 * (oc.vertex_ijk[:, 0] - 1)        # x = -1, 0, 1 -> -10, 0, 10
+    o = np.array([[-1.02, -0.5, -0.5]], np.float32)
+    d = np.array([[1.0, 0.0, 0.0]], np.float32)
+    hits, (rgb, dep, acc, st) = _render_one(oc, F, p, widths, o, d)
+    assert st.X.shape[0] == 2
+    np.testing.assert_allclose(st.X[:, 0], [-5.0, 5.0], rtol=1e-12)
+    assert st.c[0, 0] < 0.01 and st.c[1, 0] > 0.99 and st.w[0, 1] > 0.5
+    front_only = np.nonzero(oc.vertex_ijk[:, 0] == 0)[0]
+    for which in range(2):
+        ups = [np.zeros((1, 3)), np.zeros(1), np.zeros(1)]
+        if which == 0:
+            ups[0][0, 0] = 1.0
+        else:
+            ups[1][0] = 1.0
+        gF, gp = render_backward(st, *ups)
+        mF, mp = render_backward_magnitude(st, *ups)
+        assert np.abs(gF[front_only]).max() > 0
+        assert np.all(mF >= np.abs(gF) * (1 - 1e-12)), which
+        assert np.all(mp >= np.abs(gp) * (1 - 1e-12)), which
+
+
+def test_gradient_magnitude_equals_gradient_without_cancellation():
+    """With one hit per ray (no suffix sums), non-negative features and
+    weights and non-negative upstream gradients, no sum in the backward mixes
+    signs, so the magnitudes equal the gradients entry by entry."""
+    oc, F, p, widths, o, d, _, _, _ = _fd_setup(12)
+    F = np.abs(F)
+    p = np.abs(p)
+    p[-1] = 0.5
+    hits = trace_hits(oc, o, d, 1)
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
+    assert st.X.shape[0] > 10
+    rng = np.random.default_rng(4)
+    g_rgb = rng.uniform(0, 1, rgb.shape)
+    g_dep = rng.uniform(0, 1, dep.shape)
+    g_acc = rng.uniform(0, 1, acc.shape)
+    gF, gp = render_backward(st, g_rgb, g_dep, g_acc)
+    mF, mp = render_backward_magnitude(st, g_rgb, g_dep, g_acc)
+    assert np.count_nonzero(gF) > 0
+    np.testing.assert_allclose(mF, gF, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(mp, gp, rtol=1e-12, atol=0)
 
 
 def test_loss_gradient_closed_form():
