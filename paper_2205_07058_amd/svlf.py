@@ -17,7 +17,9 @@ from typing import Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsvlf.so")
+# SVLF_LIBRARY names another build of the same library (the host-sanitizer
+# build of the ABI tests); by default the in-tree libsvlf.so is loaded.
+LIB_PATH = os.environ.get("SVLF_LIBRARY") or os.path.join(HERE, "libsvlf.so")
 
 MAX_DEPTH = 10
 MAX_K = 16

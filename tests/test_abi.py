@@ -206,6 +206,21 @@ def test_host_octree_matches_oracle(case):
     np.testing.assert_array_equal(srt, oc.leaf_ijk)
 
 
+def test_host_octree_threaded_sort_matches_oracle():
+    """200,000 leaves at depth 8: 1.6M corner codes, above the size from
+    which the host builder sorts with several threads."""
+    rng = np.random.default_rng(21)
+    ijk = np.unique(rng.integers(0, 256, (205000, 3)), axis=0)
+    assert 8 * ijk.shape[0] >= 1 << 20
+    sz, nodes, corners, srt = svlf.build_octree_host(ijk[rng.permutation(len(ijk))], 8)
+    oc = Octree(ijk, 8)
+    exp_nodes, offs = _expected_nodes(oc)
+    assert sz.n_leaves == oc.n_leaves and sz.n_vertices == oc.n_vertices
+    np.testing.assert_array_equal(nodes.astype(np.int64), exp_nodes)
+    np.testing.assert_array_equal(corners, oc.leaf_corners)
+    np.testing.assert_array_equal(srt, oc.leaf_ijk)
+
+
 def test_lf_validation(lib):
     """Light-field entry points reject unsupported models, NULL parameters and
     short workspaces on the host before any device work."""
