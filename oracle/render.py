@@ -163,9 +163,11 @@ def render(octree: Octree, features, params, widths, o, d, hits, tau_mode="voxel
     return rgb, depth, acc, st
 
 
-def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
-    """Hand-derived backward of ``render`` for upstream gradients of rgb,
-    depth and acc.  Returns (grad_features (n_vertices, C), grad_params)."""
+def _backward_per_hit(st, grad_rgb, grad_depth, grad_acc=None):
+    """The backward of ``render`` up to the point where per-hit quantities
+    are summed: returns, for the decoder layers (first to last), the pairs
+    (dL/dz of every hit, the layer input of every hit), and dL/dX of every
+    hit (the decoder input's feature part)."""
     n, K = st.n, st.K
     g_rgb = np.asarray(grad_rgb, np.float64).reshape(n, 3)
     g_d = np.asarray(grad_depth, np.float64).reshape(n)
@@ -191,80 +193,64 @@ def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
     # MLP backward
     layers = split_params(st.params, st.widths)
     r = bf16_round if st.bf16 else (lambda v: v)
-    grads = []
+    per_layer = []
     g_z = g_out
     for li in range(len(layers) - 1, -1, -1):
         W, b = layers[li]
-        a = st.acts[li]
         g_zr = r(g_z)
-        grads.append((g_zr.T @ a, np.sum(g_zr, axis=0)))
+        per_layer.append((g_zr, st.acts[li]))
         g_a = g_zr @ r(W)
         if li > 0:
             g_z = np.where(st.pres[li - 1] > 0.0, g_a, 0.0)
         else:
             g_X = g_a[:, :st.C]          # the view direction takes no gradient
-    grads.reverse()
-    grad_params = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    per_layer.reverse()
+    return per_layer, g_X
+
+
+def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
+    """Hand-derived backward of ``render`` for upstream gradients of rgb,
+    depth and acc.  Returns (grad_features (n_vertices, C), grad_params)."""
+    per_layer, g_X = _backward_per_hit(st, grad_rgb, grad_depth, grad_acc)
+    grad_params = np.concatenate([np.concatenate([(g_zr.T @ a).ravel(), np.sum(g_zr, axis=0)])
+                                  for g_zr, a in per_layer])
     grad_F = np.zeros((st.n_vertices, st.C))
     contrib = st.wj[:, :, None] * g_X[:, None, :]       # (m, 8, C)
     np.add.at(grad_F, st.corners.ravel(), contrib.reshape(-1, st.C))
     return grad_F, grad_params
 
 
-def render_backward_magnitude(st, mag_rgb, mag_depth, mag_acc=None):
-    """Magnitude of the terms that make up every entry of ``render_backward``.
+def render_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None):
+    """Scale of the per-hit contributions behind every entry of
+    ``render_backward`` (test infrastructure: the scale of per-entry rounding
+    bounds of another evaluation of the same sums).
 
-    The backward of Eq. 3 and of the decoder is a chain of sums: the
-    compositing gradient of a segment, dL/dtau_i = sum over channels of
-    g (T_{i+1} c_i - sum_{j>i} w_j c_j), each layer's W^T dL/dz, each
-    weight gradient's sum over hits, and the trilinear scatter into a vertex
-    row.  Here every such sum is replaced by the sum of the absolute values
-    of its terms (|W| for W, T_{i+1} c_i + S_i for the difference, and so
-    on), starting from upstream magnitudes mag_* >= |dL/d output|.  Each
-    entry of the result is therefore an upper bound of the matching
-    |gradient| (triangle inequality), with equality when no sum in the chain
-    mixes signs, and it is the scale relative to which a floating-point
-    evaluation of that entry rounds: its rounding error is at most a small
-    multiple of the unit roundoff times this magnitude, however much the
-    terms cancel.  Returns (M_features (n_vertices, C), M_params)."""
-    n, K = st.n, st.K
-    m_rgb = np.abs(np.asarray(mag_rgb, np.float64)).reshape(n, 3)
-    m_d = np.abs(np.asarray(mag_depth, np.float64)).reshape(n)
-    m_a = np.zeros(n) if mag_acc is None else np.abs(np.asarray(mag_acc, np.float64)).reshape(n)
-    T, w, tau, col, tmid = st.T, st.w, st.tau, st.col, st.tmid
-    T_next = T * np.exp(-tau)
-    # the suffix sums S_i are sums of non-negative terms
-    wc = w[:, :, None] * col
-    S_c = np.sum(wc, axis=1, keepdims=True) - np.cumsum(wc, axis=1)
-    wt = w * tmid
-    S_t = np.sum(wt, axis=1, keepdims=True) - np.cumsum(wt, axis=1)
-    S_a = np.sum(w, axis=1, keepdims=True) - np.cumsum(w, axis=1)
-    m_tau = (np.sum(m_rgb[:, None, :] * (T_next[:, :, None] * col + np.abs(S_c)), axis=2)
-             + m_d[:, None] * (T_next * np.abs(tmid) + np.abs(S_t))
-             + m_a[:, None] * (T_next + np.abs(S_a)))
-    ri, si = st.ray_i, st.slot_i
-    m_out = np.zeros_like(st.out)
-    m_out[:, 3] = np.where(st.out[:, 3] > 0.0, m_tau[ri, si] * np.abs(st.dtau), 0.0)
-    c = st.c
-    m_out[:, :3] = (w[:, :, None] * m_rgb[:, None, :])[ri, si] * c * (1.0 - c)
-    layers = split_params(st.params, st.widths)
-    r = bf16_round if st.bf16 else (lambda v: v)
+    Every gradient entry is a sum over hits: a feature row receives
+    w_j dL/dx_h from each hit h that has the vertex as corner j, a decoder
+    weight dL/dz_h[i] a_h[k] from every hit, a bias dL/dz_h[i].  Returns,
+    per entry, S + R with
+      S = the sum over those hits of |contribution|, and
+      R = the sum over those hits of the largest |contribution| the same hit
+          makes to the entry's group (a feature row: w_j max_c |dL/dx_h[c]|;
+          a layer's weights: max_i |dL/dz_h[i]| max_k |a_h[k]|; a layer's
+          biases: max_i |dL/dz_h[i]|).
+    S bounds the entry (triangle inequality), also when the hits' terms
+    cancel; R is the scale of a hit's own evaluation error, which arises
+    over the whole group (the decoder backward mixes all its units).
+    Returns (M_features (n_vertices, C), M_params)."""
+    per_layer, g_X = _backward_per_hit(st, grad_rgb, grad_depth, grad_acc)
     mags = []
-    m_z = m_out
-    for li in range(len(layers) - 1, -1, -1):
-        W, _ = layers[li]
-        a = np.abs(st.acts[li])
-        mags.append((m_z.T @ a, np.sum(m_z, axis=0)))
-        m_a_in = m_z @ np.abs(r(W))
-        if li > 0:
-            m_z = np.where(st.pres[li - 1] > 0.0, m_a_in, 0.0)
-        else:
-            m_X = m_a_in[:, :st.C]
-    mags.reverse()
-    m_params = np.concatenate([np.concatenate([mW.ravel(), mb]) for mW, mb in mags])
-    m_F = np.zeros((st.n_vertices, st.C))
-    np.add.at(m_F, st.corners.ravel(), (st.wj[:, :, None] * m_X[:, None, :]).reshape(-1, st.C))
-    return m_F, m_params
+    for g_zr, a in per_layer:
+        gz, aa = np.abs(g_zr), np.abs(a)
+        rW = float(np.sum(gz.max(axis=1, initial=0.0) * aa.max(axis=1, initial=0.0)))
+        rb = float(np.sum(gz.max(axis=1, initial=0.0)))
+        mags.append(np.concatenate([(gz.T @ aa).ravel() + rW, np.sum(gz, axis=0) + rb]))
+    M_params = np.concatenate(mags)
+    gx = np.abs(g_X)
+    row = st.wj[:, :, None] * (gx[:, None, :] + gx.max(axis=1, initial=0.0)[:, None, None])
+    M_F = np.zeros((st.n_vertices, st.C))
+    np.add.at(M_F, st.corners.ravel(), row.reshape(-1, st.C))
+    return M_F, M_params
 
 
 def loss(rgb, depth, rgb_t, depth_t, lam_depth=0.1):

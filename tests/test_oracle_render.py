@@ -16,7 +16,7 @@ import pytest
 
 from oracle.octree import Octree
 from oracle.render import (bf16_round, interpolation_weights, loss, mlp_forward,
-                           render, render_backward, render_backward_magnitude, split_params)
+                           render, render_backward, render_backward_hit_magnitude, split_params)
 from oracle.trace import trace_hits
 from synth.configs import param_count, tiny_workload, xavier_params
 from tests.helpers import crafted_occupancy, random_rays
@@ -360,97 +360,71 @@ def test_acc_gradient_and_conservation():
     assert abs(fd - float(np.sum(gF * F))) <= 1e-6 * max(1.0, abs(fd))
 
 
-def test_gradient_magnitude_bounds_every_entry():
-    """The term magnitudes of the backward bound every gradient entry
-    (triangle inequality), also where the terms cancel, and scale linearly
-    with the upstream magnitudes."""
+def test_hit_magnitude_bounds_every_entry_and_is_homogeneous():
+    """The per-hit contribution scale bounds every gradient entry (triangle
+    inequality), also where the hits' terms cancel, and scales linearly with
+    the upstream gradients."""
     oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
     rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
     rng = np.random.default_rng(3)
-    g_rgb = rng.normal(size=rgb.shape)
-    g_dep = rng.normal(size=dep.shape)
-    g_acc = rng.normal(size=acc.shape)
-    gF, gp = render_backward(st, g_rgb, g_dep, g_acc)
-    mF, mp = render_backward_magnitude(st, np.abs(g_rgb), np.abs(g_dep), np.abs(g_acc))
-    assert np.all(mF >= np.abs(gF) * (1 - 1e-12)) and np.all(mp >= np.abs(gp) * (1 - 1e-12))
-    # the terms do cancel on this scene (several hits per ray, mixed signs)
-    assert np.median((np.abs(gF) / np.maximum(mF, 1e-300))[mF > 0]) < 0.9
-    mF2, mp2 = render_backward_magnitude(st, 2 * np.abs(g_rgb), 2 * np.abs(g_dep), 2 * np.abs(g_acc))
+    ups = [rng.normal(size=rgb.shape), rng.normal(size=dep.shape), rng.normal(size=acc.shape)]
+    gF, gp = render_backward(st, *ups)
+    mF, mp = render_backward_hit_magnitude(st, *ups)
+    assert np.all(mF >= np.abs(gF)) and np.all(mp >= np.abs(gp))
+    assert np.all(mF[np.any(gF != 0, axis=1)] > 0)
+    mF2, mp2 = render_backward_hit_magnitude(st, *[2 * u for u in ups])
     np.testing.assert_allclose(mF2, 2 * mF, rtol=1e-14, atol=0)
     np.testing.assert_allclose(mp2, 2 * mp, rtol=1e-14, atol=0)
-    # each upstream output alone, on a near-opaque decoder: the later
-    # segments' share of the colour (the suffix sums) then dominates the
-    # compositing gradient of the first segments
-    p = p.copy()
-    p[-1] = 3.0
-    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
-    for which in range(3):
-        ups = [np.zeros_like(rgb), np.zeros_like(dep), np.zeros_like(acc)]
-        ups[which] = rng.normal(size=ups[which].shape)
-        gF, gp = render_backward(st, *ups)
-        mF, mp = render_backward_magnitude(st, *[np.abs(u) for u in ups])
-        assert np.all(mF >= np.abs(gF) * (1 - 1e-12)) and np.all(mp >= np.abs(gp) * (1 - 1e-12)), which
+    # the sign of the upstream gradients does not matter
+    mF3, mp3 = render_backward_hit_magnitude(st, *[-u for u in ups])
+    np.testing.assert_allclose(mF3, mF, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(mp3, mp, rtol=1e-14, atol=0)
 
 
-def test_gradient_magnitude_dark_voxel_before_bright_one():
-    """Two leaves along a ray, a dark nearly transparent voxel in front of a
-    bright dense one: the gradient of the first voxel's optical thickness is
-    almost entirely the later voxel's share (the suffix sum of Eq. 3's
-    backward), so a magnitude without that share would fall below the
-    gradient of the first leaf's own corner features."""
-    oc = Octree([[0, 0, 0], [1, 0, 0]], 1)
-    C = 4
-    widths = (C, 4, 4)
-    p = np.zeros(param_count(widths))
-    W = split_params(p, widths)
-    W[0][0][:] = np.eye(4)
-    W[0][1][0] = 10.0             # h_0 = relu(x_0 + 10)
-    W[1][0][0, 0] = 1.0           # o_0 = h_0 - 10: colour follows x_0
-    W[1][1][0] = -10.0
-    W[1][0][3, 0] = 0.2           # sigma = relu(0.2 h_0 - 0.5)
-    W[1][1][3] = -0.5
-    F = np.zeros((oc.n_vertices, C))
-    F[:, 0] = 10.0 * (oc.vertex_ijk[:, 0] - 1)        # x = -1, 0, 1 -> -10, 0, 10
-    o = np.array([[-1.02, -0.5, -0.5]], np.float32)
-    d = np.array([[1.0, 0.0, 0.0]], np.float32)
-    hits, (rgb, dep, acc, st) = _render_one(oc, F, p, widths, o, d)
-    assert st.X.shape[0] == 2
-    np.testing.assert_allclose(st.X[:, 0], [-5.0, 5.0], rtol=1e-12)
-    assert st.c[0, 0] < 0.01 and st.c[1, 0] > 0.99 and st.w[0, 1] > 0.5
-    front_only = np.nonzero(oc.vertex_ijk[:, 0] == 0)[0]
-    for which in range(2):
-        ups = [np.zeros((1, 3)), np.zeros(1), np.zeros(1)]
-        if which == 0:
-            ups[0][0, 0] = 1.0
-        else:
-            ups[1][0] = 1.0
-        gF, gp = render_backward(st, *ups)
-        mF, mp = render_backward_magnitude(st, *ups)
-        assert np.abs(gF[front_only]).max() > 0
-        assert np.all(mF >= np.abs(gF) * (1 - 1e-12)), which
-        assert np.all(mp >= np.abs(gp) * (1 - 1e-12)), which
-
-
-def test_gradient_magnitude_equals_gradient_without_cancellation():
-    """With one hit per ray (no suffix sums), non-negative features and
-    weights and non-negative upstream gradients, no sum in the backward mixes
-    signs, so the magnitudes equal the gradients entry by entry."""
+def test_hit_magnitude_of_one_hit():
+    """One ray with one hit: every entry receives a single contribution, so
+    the scale is |gradient| plus the largest |gradient| of the entry's group
+    (the vertex row; the layer's weights; the layer's biases), both read off
+    the oracle's gradient itself."""
     oc, F, p, widths, o, d, _, _, _ = _fd_setup(12)
-    F = np.abs(F)
-    p = np.abs(p)
-    p[-1] = 0.5
     hits = trace_hits(oc, o, d, 1)
-    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
-    assert st.X.shape[0] > 10
-    rng = np.random.default_rng(4)
-    g_rgb = rng.uniform(0, 1, rgb.shape)
-    g_dep = rng.uniform(0, 1, dep.shape)
-    g_acc = rng.uniform(0, 1, acc.shape)
-    gF, gp = render_backward(st, g_rgb, g_dep, g_acc)
-    mF, mp = render_backward_magnitude(st, g_rgb, g_dep, g_acc)
-    assert np.count_nonzero(gF) > 0
-    np.testing.assert_allclose(mF, gF, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(mp, gp, rtol=1e-12, atol=0)
+    r = int(np.nonzero(hits[3] > 0)[0][0])
+    h1 = tuple(x[r:r + 1] for x in hits)
+    rgb, dep, acc, st = render(oc, F, p, widths, o[r:r + 1], d[r:r + 1], h1)
+    assert st.X.shape[0] == 1
+    ups = [np.array([[0.3, -1.2, 0.7]]), np.array([0.4]), np.array([-0.9])]
+    gF, gp = render_backward(st, *ups)
+    mF, mp = render_backward_hit_magnitude(st, *ups)
+    exp_F = np.abs(gF) + np.abs(gF).max(axis=1, keepdims=True)
+    np.testing.assert_allclose(mF, exp_F, rtol=1e-13, atol=0)
+    exp_p, off = [], 0
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        gW = np.abs(gp[off:off + fi * fo])
+        gb = np.abs(gp[off + fi * fo:off + fi * fo + fo])
+        exp_p += [gW + gW.max(), gb + gb.max()]
+        off += fi * fo + fo
+    np.testing.assert_allclose(mp, np.concatenate(exp_p), rtol=1e-13, atol=0)
+
+
+def test_hit_magnitude_adds_over_cancelling_hits():
+    """The same rays twice with opposite upstream gradients: the gradients
+    cancel exactly, the scale is twice that of one copy (it adds over hits,
+    whatever their signs)."""
+    oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
+    rng = np.random.default_rng(5)
+    ups = [rng.normal(size=(o.shape[0], 3)), rng.normal(size=o.shape[0]), rng.normal(size=o.shape[0])]
+    _, _, _, st1 = render(oc, F, p, widths, o, d, hits)
+    m1F, m1p = render_backward_hit_magnitude(st1, *ups)
+    o2, d2 = np.concatenate([o, o]), np.concatenate([d, d])
+    h2 = tuple(np.concatenate([x, x]) for x in hits)
+    _, _, _, st2 = render(oc, F, p, widths, o2, d2, h2)
+    ups2 = [np.concatenate([u, -u]) for u in ups]
+    gF, gp = render_backward(st2, *ups2)
+    m2F, m2p = render_backward_hit_magnitude(st2, *ups2)
+    assert np.abs(gF).max() <= 1e-15 * np.abs(m2F).max() and np.abs(gp).max() <= 1e-15 * np.abs(m2p).max()
+    np.testing.assert_allclose(m2F, 2 * m1F, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(m2p, 2 * m1p, rtol=1e-13, atol=0)
+    assert m1F.max() > 0 and m1p.max() > 0
 
 
 def test_loss_gradient_closed_form():
