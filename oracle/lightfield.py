@@ -99,22 +99,24 @@ def _mlp(layers, X, rnd):
     raise ValueError("empty MLP")
 
 
-def _mlp_backward(layers, acts, pres, g_out, rnd):
-    """Returns (per-layer (gW, gb) in order, gradient of the input)."""
-    grads = []
+def _mlp_backward_terms(layers, acts, pres, g_out, rnd):
+    """Backward of ``_mlp`` up to the sums over hits: returns (per layer in
+    order, the pair (dL/dz of every hit, the layer input of every hit)),
+    gradient of the input)."""
+    terms = []
     g_z = g_out
     g_in = None
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
         g_zr = rnd(g_z)
-        grads.append((g_zr.T @ acts[li], np.sum(g_zr, axis=0)))
+        terms.append((g_zr, acts[li]))
         g_a = g_zr @ rnd(W)
         if li > 0:
             g_z = np.where(pres[li - 1] > 0.0, g_a, 0.0)
         else:
             g_in = g_a
-    grads.reverse()
-    return grads, g_in
+    terms.reverse()
+    return terms, g_in
 
 
 def weight_derivatives(u):
@@ -271,11 +273,12 @@ def stage_loss(st, hits, rgb, t_rgb, t_depth, kind, lam_eta=1.0, lam_tau=0.0, lo
     return L, g_rgb, (g_c, g_eta, g_tau)
 
 
-def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
-    """Hand-derived backward of ``render_lf``.  ``hit_grads`` = per-hit
-    direct gradients (dL/dc, dL/deta, dL/dtau) added to those coming through
-    the compositing (``stage_loss``).  Returns (grad_features
-    (n_vertices, C_T + C_C), grad_params)."""
+def _lf_backward_per_hit(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
+    """The backward of ``render_lf`` up to the point where per-hit quantities
+    are summed: returns the per-layer pairs (dL/dz of every hit, the layer
+    input of every hit) of the density decoder and of the colour decoder,
+    and per hit dL/dpsi(x1), dL/dpsi(x2) (Z_T part) and dL/dpsi(x_s) (Z_C
+    part)."""
     ct, cc = st.dec[0], st.dec[1]
     rnd = bf16_round if st.bf16 else (lambda v: v)
     n = st.n
@@ -302,7 +305,7 @@ def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
         g_tau_hit = g_tau_hit + hit_grads[2]
     # colour decoder
     gC_out = g_c * st.c * (1.0 - st.c)
-    gradsC, g_XC = _mlp_backward(st.lc, st.actsC, st.presC, gC_out, rnd)
+    termsC, g_XC = _mlp_backward_terms(st.lc, st.actsC, st.presC, gC_out, rnd)
     g_zC = g_XC[:, :cc]
     # gradient through the sample point: psi(x_s) = sum_j w_j(u_s) F_j
     dw = weight_derivatives(st.us)                       # (m, 8, 3)
@@ -315,14 +318,64 @@ def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
     gT_out = np.zeros_like(st.oT)
     gT_out[:, 0] = np.where(st.oT[:, 0] > 0.0, g_tau_hit * st.dtau, 0.0)
     gT_out[:, 1] = g_eta * st.eta * (1.0 - st.eta)
-    gradsT, g_XT = _mlp_backward(st.lt, st.actsT, st.presT, gT_out, rnd)
+    termsT, g_XT = _mlp_backward_terms(st.lt, st.actsT, st.presT, gT_out, rnd)
     g_z1, g_z2 = g_XT[:, :ct], g_XT[:, ct:2 * ct]
+    return termsT, termsC, g_z1, g_z2, g_zC
+
+
+def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
+    """Hand-derived backward of ``render_lf``.  ``hit_grads`` = per-hit
+    direct gradients (dL/dc, dL/deta, dL/dtau) added to those coming through
+    the compositing (``stage_loss``).  Returns (grad_features
+    (n_vertices, C_T + C_C), grad_params)."""
+    ct, cc = st.dec[0], st.dec[1]
+    termsT, termsC, g_z1, g_z2, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth, grad_acc,
+                                                            hit_grads)
     grad_F = np.zeros((st.n_vertices, st.C))
     cT = st.w1[:, :, None] * g_z1[:, None, :] + st.w2[:, :, None] * g_z2[:, None, :]
     np.add.at(grad_F[:, :ct], st.corners.ravel(), cT.reshape(-1, ct))
     cC = st.ws[:, :, None] * g_zC[:, None, :]
     np.add.at(grad_F[:, ct:], st.corners.ravel(), cC.reshape(-1, cc))
     flat = []
-    for gW, gb in gradsT + gradsC:
-        flat += [gW.ravel(), gb]
+    for g_zr, a in termsT + termsC:
+        flat += [(g_zr.T @ a).ravel(), np.sum(g_zr, axis=0)]
     return grad_F, np.concatenate(flat)
+
+
+def render_lf_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
+    """Scale of the per-hit contributions behind every entry of
+    ``render_lf_backward`` (test infrastructure: the scale of per-entry
+    rounding bounds of another evaluation of the same sums), as
+    ``render.render_backward_hit_magnitude`` gives it for the single decoder.
+
+    A Z_T row receives from each hit that has the vertex as corner j the two
+    terms w1_j dL/dpsi(x1) and w2_j dL/dpsi(x2), a Z_C row ws_j dL/dpsi(x_s),
+    a weight of either decoder dL/dz_h[i] a_h[k], a bias dL/dz_h[i].  Per
+    entry the result is S + R: S = the sum over those terms of |term|
+    (it bounds the entry, also when the terms cancel); R = the sum over the
+    same terms of the largest |term| of the entry's group that the hit's
+    same factor makes (a feature block of the row: w_j max_c |dL/dpsi[c]|; a
+    layer's weights: max_i |dL/dz_h[i]| max_k |a_h[k]|; a layer's biases:
+    max_i |dL/dz_h[i]|).  Returns (M_features (n_vertices, C_T + C_C),
+    M_params)."""
+    ct = st.dec[0]
+    termsT, termsC, g_z1, g_z2, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth, grad_acc,
+                                                            hit_grads)
+    mags = []
+    for g_zr, a in termsT + termsC:
+        gz, aa = np.abs(g_zr), np.abs(a)
+        gmax = gz.max(axis=1, initial=0.0)
+        rW = float(np.sum(gmax * aa.max(axis=1, initial=0.0)))
+        rb = float(np.sum(gmax))
+        mags += [(gz.T @ aa).ravel() + rW, np.sum(gz, axis=0) + rb]
+    M_F = np.zeros((st.n_vertices, st.C))
+
+    def part(wj, g):
+        ga = np.abs(g)
+        return wj[:, :, None] * (ga[:, None, :] + ga.max(axis=1, initial=0.0)[:, None, None])
+
+    mT = part(st.w1, g_z1) + part(st.w2, g_z2)
+    np.add.at(M_F[:, :ct], st.corners.ravel(), mT.reshape(-1, ct))
+    mC = part(st.ws, g_zC)
+    np.add.at(M_F[:, ct:], st.corners.ravel(), mC.reshape(-1, g_zC.shape[1]))
+    return M_F, np.concatenate(mags)

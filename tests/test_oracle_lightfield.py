@@ -8,7 +8,8 @@ conservation identities of the feature gradients."""
 import numpy as np
 import pytest
 
-from oracle.lightfield import (n_params, render_lf, render_lf_backward, sphere_param, widths_of)
+from oracle.lightfield import (n_params, render_lf, render_lf_backward, render_lf_backward_hit_magnitude,
+                               sphere_param, widths_of)
 from oracle.octree import Octree
 from oracle.render import loss
 from oracle.trace import trace_hits
@@ -329,6 +330,89 @@ def test_feature_gradient_conservation():
     r2 = render_lf(oc, Fm, p, dec, o, d, hits)
     fd = (np.sum(g_rgb * (r1[0] - r2[0])) + np.sum(g_dep * (r1[1] - r2[1]))) / (2 * eps)
     assert abs(fd - gF[:, :4].sum(axis=0) @ e) <= 1e-6 * abs(fd) + 1e-8
+
+
+def test_lf_hit_magnitude_bounds_every_entry_and_is_homogeneous():
+    """The per-hit contribution scale of the light-field backward bounds every
+    gradient entry (triangle inequality), is linear in the upstream gradients
+    and does not depend on their sign."""
+    oc, F, p, dec, o, d, hits, _, _ = _fd_case(5, "voxel")
+    rgb, dep, acc, st = render_lf(oc, F, p, dec, o, d, hits, tau_mode="voxel")
+    rng = np.random.default_rng(3)
+    ups = [rng.normal(size=rgb.shape), rng.normal(size=dep.shape), rng.normal(size=acc.shape)]
+    gF, gp = render_lf_backward(st, *ups)
+    mF, mp = render_lf_backward_hit_magnitude(st, *ups)
+    assert np.all(mF >= np.abs(gF)) and np.all(mp >= np.abs(gp))
+    assert np.all(mF[gF != 0] > 0) and np.count_nonzero(gF) > 100
+    mF2, mp2 = render_lf_backward_hit_magnitude(st, *[2 * u for u in ups])
+    np.testing.assert_allclose(mF2, 2 * mF, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(mp2, 2 * mp, rtol=1e-14, atol=0)
+    mF3, mp3 = render_lf_backward_hit_magnitude(st, *[-u for u in ups])
+    np.testing.assert_allclose(mF3, mF, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(mp3, mp, rtol=1e-14, atol=0)
+
+
+def test_lf_hit_magnitude_of_one_hit():
+    """One ray, one hit.  Colour block and decoder parameters receive one
+    term per entry: the scale is |gradient| plus the largest |gradient| of
+    the entry's group, read off the gradient.  A Z_T row of corner j receives
+    w1_j g1 + w2_j g2 (g1, g2 = dL/dpsi at the entry and exit points): g1 and
+    g2 are recovered from the gradient by least squares over the 8 corners
+    (the weights are the textbook trilinear ones) and the scale is
+    w1_j (|g1| + max|g1|) + w2_j (|g2| + max|g2|)."""
+    oc, F, p, dec, o, d, _, _, _ = _fd_case(5, "direct")
+    hits = trace_hits(oc, o, d, 1)
+    ct, cc = dec[0], dec[1]
+    wt, wc = widths_of(dec)
+    # a ray whose entry and exit weights differ (well-posed recovery)
+    for r in np.nonzero(hits[3] > 0)[0]:
+        h1 = tuple(x[r:r + 1] for x in hits)
+        rgb, dep, acc, st = render_lf(oc, F, p, dec, o[r:r + 1], d[r:r + 1], h1)
+        if np.linalg.matrix_rank(np.stack([st.w1[0], st.w2[0]], axis=1), tol=1e-3) == 2:
+            break
+    assert st.ray_i.size == 1
+    ups = [np.array([[0.3, -1.2, 0.7]]), np.array([0.4]), np.array([-0.9])]
+    gF, gp = render_lf_backward(st, *ups)
+    mF, mp = render_lf_backward_hit_magnitude(st, *ups)
+    corners = st.corners[0]
+    gC = gF[corners, ct:]
+    np.testing.assert_allclose(mF[corners, ct:], np.abs(gC) + np.abs(gC).max(axis=1, keepdims=True),
+                               rtol=1e-13, atol=0)
+    A = np.stack([st.w1[0], st.w2[0]], axis=1)                 # (8, 2)
+    g12, *_ = np.linalg.lstsq(A, gF[corners, :ct], rcond=None)
+    np.testing.assert_allclose(A @ g12, gF[corners, :ct], rtol=1e-9, atol=1e-12)
+    exp_T = sum(A[:, k:k + 1] * (np.abs(g12[k])[None, :] + np.abs(g12[k]).max()) for k in range(2))
+    np.testing.assert_allclose(mF[corners, :ct], exp_T, rtol=1e-8, atol=1e-14)
+    others = np.setdiff1d(np.arange(F.shape[0]), corners)
+    assert np.all(mF[others] == 0)
+    exp_p, off = [], 0
+    for widths in (wt, wc):
+        for fi, fo in zip(widths[:-1], widths[1:]):
+            gW = np.abs(gp[off:off + fi * fo])
+            gb = np.abs(gp[off + fi * fo:off + fi * fo + fo])
+            exp_p += [gW + gW.max(), gb + gb.max()]
+            off += fi * fo + fo
+    np.testing.assert_allclose(mp, np.concatenate(exp_p), rtol=1e-13, atol=0)
+
+
+def test_lf_hit_magnitude_adds_over_cancelling_hits():
+    """The same rays twice with opposite upstream gradients: the gradients
+    cancel exactly and the scale is twice that of one copy."""
+    oc, F, p, dec, o, d, hits, _, _ = _fd_case(7, "direct")
+    rng = np.random.default_rng(5)
+    ups = [rng.normal(size=(o.shape[0], 3)), rng.normal(size=o.shape[0]), rng.normal(size=o.shape[0])]
+    _, _, _, st1 = render_lf(oc, F, p, dec, o, d, hits)
+    m1F, m1p = render_lf_backward_hit_magnitude(st1, *ups)
+    o2, d2 = np.concatenate([o, o]), np.concatenate([d, d])
+    h2 = tuple(np.concatenate([x, x]) for x in hits)
+    _, _, _, st2 = render_lf(oc, F, p, dec, o2, d2, h2)
+    ups2 = [np.concatenate([u, -u]) for u in ups]
+    gF, gp = render_lf_backward(st2, *ups2)
+    m2F, m2p = render_lf_backward_hit_magnitude(st2, *ups2)
+    assert np.abs(gF).max() <= 1e-15 * m2F.max() and np.abs(gp).max() <= 1e-15 * m2p.max()
+    np.testing.assert_allclose(m2F, 2 * m1F, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(m2p, 2 * m1p, rtol=1e-13, atol=0)
+    assert m1F[:, :4].max() > 0 and m1F[:, 4:].max() > 0 and m1p.max() > 0
 
 
 # ------------------------------------------------------------ staged losses (section 4.4)
