@@ -342,6 +342,24 @@ def render_lf_backward(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
     return grad_F, np.concatenate(flat)
 
 
+def render_lf_backward_weight_scale(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
+    """As ``render.render_backward_weight_scale`` for the light-field
+    backward: a Z_T entry sums D1_j |dL/dpsi(x1)[c]| + D2_j |dL/dpsi(x2)[c]|
+    over the hits that reach it, a Z_C entry D_s,j |dL/dpsi(x_s)[c]|, with
+    D = sum over axes of |d w_j / d u_a| at the entry point, the exit point
+    and the surface point (test infrastructure: the scale of the part of a
+    rounding bound due to errors in those points' cell coordinates)."""
+    ct = st.dec[0]
+    _, _, g_z1, g_z2, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth, grad_acc, hit_grads)
+    D1, D2, Ds = (np.sum(np.abs(weight_derivatives(u)), axis=2) for u in (st.u1, st.u2, st.us))
+    M_w = np.zeros((st.n_vertices, st.C))
+    mT = D1[:, :, None] * np.abs(g_z1)[:, None, :] + D2[:, :, None] * np.abs(g_z2)[:, None, :]
+    np.add.at(M_w[:, :ct], st.corners.ravel(), mT.reshape(-1, ct))
+    mC = Ds[:, :, None] * np.abs(g_zC)[:, None, :]
+    np.add.at(M_w[:, ct:], st.corners.ravel(), mC.reshape(-1, g_zC.shape[1]))
+    return M_w
+
+
 def render_lf_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
     """Scale of the per-hit contributions behind every entry of
     ``render_lf_backward`` (test infrastructure: the scale of per-entry

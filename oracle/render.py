@@ -98,6 +98,22 @@ def interpolation_weights(u):
     return w
 
 
+def weight_sensitivity(u):
+    """D (n, 8): sum over the axes a of |d w_j / d u_a| for the textbook
+    trilinear weights, i.e. how strongly corner j's weight responds to an
+    error in the cell coordinates of the sample point (d w_j / d u_a is the
+    product of the other two axes' factors, with the sign of bit a of j)."""
+    D = np.zeros((u.shape[0], 8))
+    for j in range(8):
+        for a in range(3):
+            other = np.ones(u.shape[0])
+            for b in range(3):
+                if b != a:
+                    other *= u[:, b] if (j >> b) & 1 else 1.0 - u[:, b]
+            D[:, j] += other
+    return D
+
+
 class RenderState:
     """Everything the backward needs (dense [n_rays, K] layout)."""
 
@@ -155,7 +171,7 @@ def render(octree: Octree, features, params, widths, o, d, hits, tau_mode="voxel
     acc = np.sum(w, axis=1)
     st = RenderState()
     st.__dict__.update(dict(octree=octree, widths=tuple(widths), params=np.asarray(params, np.float64),
-                            bf16=bf16, n=n, K=K, ray_i=ray_i, slot_i=slot_i, wj=wj,
+                            bf16=bf16, n=n, K=K, ray_i=ray_i, slot_i=slot_i, u=u, wj=wj,
                             corners=corners, X=X, out=out, acts=acts, pres=pres, c=c,
                             sigma=sigma, dtau=dtau, tau=tau, col=col, tmid=tmid, T=T,
                             w=w, rgb=rgb, depth=depth, acc=acc, n_vertices=F.shape[0],
@@ -251,6 +267,21 @@ def render_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None):
     M_F = np.zeros((st.n_vertices, st.C))
     np.add.at(M_F, st.corners.ravel(), row.reshape(-1, st.C))
     return M_F, M_params
+
+
+def render_backward_weight_scale(st, grad_rgb, grad_depth, grad_acc=None):
+    """Per entry of the feature gradient of ``render_backward``, the sum over
+    the hits that reach it of D_j |dL/dx_h[c]| (``weight_sensitivity`` of
+    the hit's sample point; test infrastructure).  An error e in the cell
+    coordinates of a hit's sample point moves the hit's contribution to the
+    entry by at most e D_j |dL/dx_h[c]|: this is the scale of that part of a
+    rounding bound, which a weight near zero (a sample point near a face of
+    its cell) would otherwise make unbounded relative to the contribution."""
+    _, g_X = _backward_per_hit(st, grad_rgb, grad_depth, grad_acc)
+    D = weight_sensitivity(st.u)
+    M_w = np.zeros((st.n_vertices, st.C))
+    np.add.at(M_w, st.corners.ravel(), (D[:, :, None] * np.abs(g_X)[:, None, :]).reshape(-1, st.C))
+    return M_w
 
 
 def loss(rgb, depth, rgb_t, depth_t, lam_depth=0.1):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle.lightfield import (n_params, render_lf, render_lf_backward, render_lf_backward_hit_magnitude,
-                               sphere_param, widths_of)
+                               render_lf_backward_weight_scale, sphere_param, weight_derivatives, widths_of)
 from oracle.octree import Octree
 from oracle.render import loss
 from oracle.trace import trace_hits
@@ -413,6 +413,58 @@ def test_lf_hit_magnitude_adds_over_cancelling_hits():
     np.testing.assert_allclose(m2F, 2 * m1F, rtol=1e-13, atol=0)
     np.testing.assert_allclose(m2p, 2 * m1p, rtol=1e-13, atol=0)
     assert m1F[:, :4].max() > 0 and m1F[:, 4:].max() > 0 and m1p.max() > 0
+
+
+def test_lf_weight_scale_of_one_hit_and_over_cancelling_hits():
+    """One ray, one hit: a Z_C row of corner j has the weight scale
+    D_s,j |dL/dpsi(x_s)| with dL/dpsi(x_s) = Z_C gradient row / w_s,j, and a Z_T
+    row D1_j |g1| + D2_j |g2| with g1, g2 recovered from the Z_T gradient by
+    least squares over the trilinear weights (D from the weights' central
+    differences).  Opposite upstream gradients on duplicated rays double it."""
+    from oracle.render import interpolation_weights
+    oc, F, p, dec, o, d, _, _, _ = _fd_case(5, "direct")
+    hits = trace_hits(oc, o, d, 1)
+    ct = dec[0]
+    for r in np.nonzero(hits[3] > 0)[0]:
+        h1 = tuple(x[r:r + 1] for x in hits)
+        _, _, _, st = render_lf(oc, F, p, dec, o[r:r + 1], d[r:r + 1], h1)
+        A = np.stack([st.w1[0], st.w2[0]], axis=1)
+        if np.linalg.matrix_rank(A, tol=1e-3) == 2 and np.all(st.ws[0] > 1e-6):
+            break
+    ups = [np.array([[0.3, -1.2, 0.7]]), np.array([0.4]), np.array([-0.9])]
+    gF, _ = render_lf_backward(st, *ups)
+    Mw = render_lf_backward_weight_scale(st, *ups)
+
+    def fd_D(u):
+        D = np.zeros(8)
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = 1e-7
+            D += np.abs((interpolation_weights(u + e) - interpolation_weights(u - e))[0] / 2e-7)
+        return D
+
+    corners = st.corners[0]
+    Ds = fd_D(st.us)
+    np.testing.assert_allclose(Mw[corners, ct:], Ds[:, None] * np.abs(gF[corners, ct:]) / st.ws[0][:, None],
+                               rtol=1e-6)
+    g12, *_ = np.linalg.lstsq(A, gF[corners, :ct], rcond=None)
+    exp_T = fd_D(st.u1)[:, None] * np.abs(g12[0])[None, :] + fd_D(st.u2)[:, None] * np.abs(g12[1])[None, :]
+    np.testing.assert_allclose(Mw[corners, :ct], exp_T, rtol=1e-5, atol=1e-12)
+    oc, F, p, dec, o, d, hits, _, _ = _fd_case(7, "direct")
+    rng = np.random.default_rng(5)
+    ups = [rng.normal(size=(o.shape[0], 3)), rng.normal(size=o.shape[0]), rng.normal(size=o.shape[0])]
+    _, _, _, st1 = render_lf(oc, F, p, dec, o, d, hits)
+    m1 = render_lf_backward_weight_scale(st1, *ups)
+    h2 = tuple(np.concatenate([x, x]) for x in hits)
+    _, _, _, st2 = render_lf(oc, F, p, dec, np.concatenate([o, o]), np.concatenate([d, d]), h2)
+    m2 = render_lf_backward_weight_scale(st2, *[np.concatenate([u_, -u_]) for u_ in ups])
+    np.testing.assert_allclose(m2, 2 * m1, rtol=1e-13, atol=0)
+    assert m1[:, :ct].max() > 0 and m1[:, ct:].max() > 0
+    # the derivative table used for D agrees with central differences
+    u = np.random.default_rng(1).uniform(0.1, 0.9, (5, 3))
+    for i in range(5):
+        np.testing.assert_allclose(np.sum(np.abs(weight_derivatives(u[i:i + 1])[0]), axis=1), fd_D(u[i:i + 1]),
+                                   rtol=1e-6)
 
 
 # ------------------------------------------------------------ staged losses (section 4.4)

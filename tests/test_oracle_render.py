@@ -16,7 +16,8 @@ import pytest
 
 from oracle.octree import Octree
 from oracle.render import (bf16_round, interpolation_weights, loss, mlp_forward,
-                           render, render_backward, render_backward_hit_magnitude, split_params)
+                           render, render_backward, render_backward_hit_magnitude,
+                           render_backward_weight_scale, split_params, weight_sensitivity)
 from oracle.trace import trace_hits
 from synth.configs import param_count, tiny_workload, xavier_params
 from tests.helpers import crafted_occupancy, random_rays
@@ -425,6 +426,54 @@ def test_hit_magnitude_adds_over_cancelling_hits():
     np.testing.assert_allclose(m2F, 2 * m1F, rtol=1e-13, atol=0)
     np.testing.assert_allclose(m2p, 2 * m1p, rtol=1e-13, atol=0)
     assert m1F.max() > 0 and m1p.max() > 0
+
+
+def test_weight_sensitivity_against_finite_differences_and_closed_forms():
+    """D_j = sum over axes of |d w_j / d u_a| of the trilinear weights: central
+    differences of the weights at random points, 3/4 for every corner at the
+    cell centre, and (3, 1, 1, 0, 1, 0, 0, 0) at the corner u = 0."""
+    rng = np.random.default_rng(0)
+    u = rng.uniform(0.05, 0.95, (200, 3))
+    D = weight_sensitivity(u)
+    fd = np.zeros_like(D)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1e-6
+        fd += np.abs((interpolation_weights(u + e) - interpolation_weights(u - e)) / 2e-6)
+    np.testing.assert_allclose(D, fd, rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(weight_sensitivity(np.full((1, 3), 0.5)), 0.75, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(weight_sensitivity(np.zeros((1, 3)))[0], [3, 1, 1, 0, 1, 0, 0, 0])
+
+
+def test_weight_scale_of_one_hit_and_over_cancelling_hits():
+    """One ray with one hit: a corner row's weight scale is D_j |dL/dx| with
+    dL/dx = gradient row / w_j (read off the gradient).  The same rays twice
+    with opposite upstream gradients: the scale doubles."""
+    oc, F, p, widths, o, d, _, _, _ = _fd_setup(12)
+    hits = trace_hits(oc, o, d, 1)
+    r = int(np.nonzero(hits[3] > 0)[0][0])
+    h1 = tuple(x[r:r + 1] for x in hits)
+    _, _, _, st = render(oc, F, p, widths, o[r:r + 1], d[r:r + 1], h1)
+    ups = [np.array([[0.3, -1.2, 0.7]]), np.array([0.4]), np.array([-0.9])]
+    gF, _ = render_backward(st, *ups)
+    Mw = render_backward_weight_scale(st, *ups)
+    corners = st.corners[0]
+    wj = interpolation_weights(st.u)[0]
+    Dj = weight_sensitivity(st.u)[0]
+    assert np.all(wj > 1e-6)
+    np.testing.assert_allclose(Mw[corners], Dj[:, None] * np.abs(gF[corners]) / wj[:, None], rtol=1e-10)
+    assert np.all(np.delete(Mw, corners, axis=0) == 0)
+    # additivity
+    oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
+    rng = np.random.default_rng(5)
+    ups = [rng.normal(size=(o.shape[0], 3)), rng.normal(size=o.shape[0]), rng.normal(size=o.shape[0])]
+    _, _, _, st1 = render(oc, F, p, widths, o, d, hits)
+    m1 = render_backward_weight_scale(st1, *ups)
+    h2 = tuple(np.concatenate([x, x]) for x in hits)
+    _, _, _, st2 = render(oc, F, p, widths, np.concatenate([o, o]), np.concatenate([d, d]), h2)
+    m2 = render_backward_weight_scale(st2, *[np.concatenate([u_, -u_]) for u_ in ups])
+    np.testing.assert_allclose(m2, 2 * m1, rtol=1e-13, atol=0)
+    assert m1.max() > 0
 
 
 def test_loss_gradient_closed_form():
