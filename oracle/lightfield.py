@@ -360,6 +360,65 @@ def render_lf_backward_weight_scale(st, grad_rgb, grad_depth, grad_acc=None, hit
     return M_w
 
 
+def density_output_term_magnitudes(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
+    """Per hit, the sums of absolute values of the terms that make up
+    dL/do_T0 and dL/do_T1 (the density decoder's output pre-activations;
+    test infrastructure: where those terms cancel, the gradient is a small
+    difference of large terms and another evaluation of it is accurate to
+    their size, not to its own).  dL/dtau = sum_ch g_ch (T_next c_ch - S_ch)
+    + g_d (T_next t_s - S_t) + g_a (T_next - S_a) (+ a direct term) gives
+    G_tau = sum_ch |g_ch| (T_next c_ch + S_ch) + |g_d| (T_next t_s + S_t) +
+    |g_a| (T_next + S_a) (+ |direct|), times dtau where o_T0 > 0; dL/deta =
+    dL/dt_s (t_in - t_out) + dL/dx_s . (x1 - x2) (+ direct) gives
+    G_eta = |dL/dt_s| |t_in - t_out| + sum_a |x1 - x2|_a G_xs,a (+ |direct|)
+    with G_xs,a = sum_j |d w_j / d u_a| sum_c |F_jc| |dL/dpsi(x_s)_c| / h
+    where the clamp passes, times eta (1 - eta).  Returns (G0, G1), each
+    (m,)."""
+    n = st.n
+    g_rgb = np.asarray(grad_rgb, np.float64).reshape(n, 3)
+    g_d = np.asarray(grad_depth, np.float64).reshape(n)
+    g_a = np.zeros(n) if grad_acc is None else np.asarray(grad_acc, np.float64).reshape(n)
+    T, w, tau, col, ts = st.T, st.w, st.tau, st.col, st.ts
+    Tn = T * np.exp(-tau)
+    wc = w[:, :, None] * col
+    S_c = np.sum(wc, axis=1, keepdims=True) - np.cumsum(wc, axis=1)
+    wt = w * ts
+    S_t = np.sum(wt, axis=1, keepdims=True) - np.cumsum(wt, axis=1)
+    S_a = np.sum(w, axis=1, keepdims=True) - np.cumsum(w, axis=1)
+    G_tau = (np.sum(np.abs(g_rgb)[:, None, :] * (Tn[:, :, None] * col + S_c), axis=2)
+             + np.abs(g_d)[:, None] * (Tn * ts + S_t) + np.abs(g_a)[:, None] * (Tn + S_a))
+    ri, si = st.ray_i, st.slot_i
+    G_tau = G_tau[ri, si]
+    G_eta_direct = np.zeros(ri.size)
+    if hit_grads is not None:
+        G_tau = G_tau + np.abs(hit_grads[2])
+        G_eta_direct = np.abs(hit_grads[1])
+    G0 = np.where(st.oT[:, 0] > 0.0, G_tau * st.dtau, 0.0)
+    _, _, _, _, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth, grad_acc, hit_grads)
+    adw = np.abs(weight_derivatives(st.us))                       # (m, 8, 3)
+    fz = np.einsum("mjc,mc->mj", np.abs(st.FC), np.abs(g_zC))      # (m, 8)
+    inside = (st.us_raw >= 0.0) & (st.us_raw <= 1.0)
+    G_xs = np.where(inside, np.einsum("mja,mj->ma", adw, fz), 0.0) / st.h
+    g_ts = np.abs(w[ri, si] * g_d[ri])
+    G_eta = g_ts * np.abs(st.t0 - st.t1) + np.sum(G_xs * np.abs(st.x1 - st.x2), axis=1) + G_eta_direct
+    G1 = G_eta * st.eta * (1.0 - st.eta)
+    return G0, G1
+
+
+def density_input_jacobian(st):
+    """Per hit, the gradient of the density decoder's input with respect to
+    each of its two outputs (the backward of a unit output gradient; the
+    hit's ReLU pattern).  Returns (J0, J1), each (m, 2 C_T + 6 [+ 3])."""
+    rnd = bf16_round if st.bf16 else (lambda v: v)
+    out = []
+    for k in range(2):
+        e = np.zeros_like(st.oT)
+        e[:, k] = 1.0
+        _, g_in = _mlp_backward_terms(st.lt, st.actsT, st.presT, e, rnd)
+        out.append(g_in)
+    return out[0], out[1]
+
+
 def render_lf_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None, hit_grads=None):
     """Scale of the per-hit contributions behind every entry of
     ``render_lf_backward`` (test infrastructure: the scale of per-entry
@@ -374,8 +433,12 @@ def render_lf_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None, hi
     same terms of the largest |term| of the entry's group that the hit's
     same factor makes (a feature block of the row: w_j max_c |dL/dpsi[c]|; a
     layer's weights: max_i |dL/dz_h[i]| max_k |a_h[k]|; a layer's biases:
-    max_i |dL/dz_h[i]|).  Returns (M_features (n_vertices, C_T + C_C),
-    M_params)."""
+    max_i |dL/dz_h[i]|).  For Z_T, dL/dpsi(x1) and dL/dpsi(x2) are taken at
+    their conditioning: |J0| G0 + |J1| G1 (``density_input_jacobian``,
+    ``density_output_term_magnitudes``) in place of their absolute values,
+    as the density decoder's two output gradients are often small
+    differences of large terms (Eq. 3's backward of an opaque ray).  Returns
+    (M_features (n_vertices, C_T + C_C), M_params)."""
     ct = st.dec[0]
     termsT, termsC, g_z1, g_z2, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth, grad_acc,
                                                             hit_grads)
@@ -392,7 +455,10 @@ def render_lf_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None, hi
         ga = np.abs(g)
         return wj[:, :, None] * (ga[:, None, :] + ga.max(axis=1, initial=0.0)[:, None, None])
 
-    mT = part(st.w1, g_z1) + part(st.w2, g_z2)
+    G0, G1 = density_output_term_magnitudes(st, grad_rgb, grad_depth, grad_acc, hit_grads)
+    J0, J1 = density_input_jacobian(st)
+    A = np.abs(J0) * G0[:, None] + np.abs(J1) * G1[:, None]
+    mT = part(st.w1, A[:, :ct]) + part(st.w2, A[:, ct:2 * ct])
     np.add.at(M_F[:, :ct], st.corners.ravel(), mT.reshape(-1, ct))
     mC = part(st.ws, g_zC)
     np.add.at(M_F[:, ct:], st.corners.ravel(), mC.reshape(-1, g_zC.shape[1]))
