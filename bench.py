@@ -11,10 +11,15 @@ trilinear interpolation, decoder, Eq. 3 compositing, MSE + L1 loss and the
 hand-written backward (svlf_train_step) with the BF16 decoder.  Also
 reported: the same step with the FP32 decoder, the forward render of one
 1600^2 view (BF16 and FP32), whole optimisation steps with dense and with
-lazy (touched-row) Adam on the features, per-kernel
-durations (HIP events on the launch stream) with the roofline of the
-dominant kernel, PSNR of the BF16 render against the FP64 oracle on a seeded
-ray sample, and the oracle itself timed on the host.
+lazy (touched-row) Adam on the features, per-kernel durations (HIP events on
+the launch stream) with the roofline of the dominant kernel against the HBM
+peak and against the bandwidth of a plain device copy; the other workloads
+(the depth-4 shell and the depth-7 ellipsoid views forward, the depth-7
+2^18-ray training batch, the ragged batch of 8 scenes of depths 7-10 in one
+launch and from a HIP graph); the light-field function; PSNR of the BF16
+and FP32 renders of a trained network against the FP64 oracle, and the
+held-out PSNR of BF16- and FP32-trained networks; the oracle itself timed on
+the host cores (a process pool in a child process).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -107,9 +112,15 @@ def parse():
                     help="rays of the batch the oracle trains on for the CPU baseline")
     ap.add_argument("--psnr-rays", type=int, default=16384)
     ap.add_argument("--sections", default="all",
-                    help="comma list of: train_bf16,train_fp32,fwd_bf16,fwd_fp32,adam,stages,psnr,lf,occ,det,copy,"
-                         "multi (the ragged 8-scene workload; not in 'all')")
+                    help="comma list of: " + ",".join(ALL_SECTIONS))
+    ap.add_argument("--train-steps", type=int, default=200,
+                    help="optimisation steps of the networks whose PSNR is reported")
+    ap.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
+
+
+ALL_SECTIONS = ("train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "copy", "stages", "adam", "lf", "occ",
+                "det", "small", "multi", "psnr")
 
 
 class Timer:
@@ -136,6 +147,8 @@ class Timer:
 
 def main():
     args = parse()
+    if args.cpu_child:
+        return cpu_child(args.cpu_child)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
                  "(the sharding design is described in DESIGN.md); run with --gpus 1")
@@ -144,8 +157,7 @@ def main():
     from paper_2205_07058_amd import svlf
     from synth.configs import get_config
 
-    sections = set(args.sections.split(",")) if args.sections != "all" else {
-        "train_bf16", "train_fp32", "fwd_bf16", "fwd_fp32", "adam", "stages", "psnr", "lf", "occ", "det"}
+    sections = set(args.sections.split(",")) if args.sections != "all" else set(ALL_SECTIONS)
     torch.cuda.set_device(0)
     svlf.load()
     t0 = time.time()
@@ -286,31 +298,13 @@ def main():
         log(f"stages (bf16 train): trace {stages['trace_ms']:.3f} ms, "
             f"shade+reduce {stages['shade_reduce_ms']:.3f} ms")
 
-    psnr = None
-    if "psnr" in sections:
-        from oracle.octree import Octree
-        from oracle.render import render as oracle_render
-        from oracle.trace import trace_hits as oracle_trace
-        rgb16 = torch.empty((n_v, 3), device="cuda")
-        svlf.render([scene], [n_v], params, w.widths, svlf.make_opts(w.K, "voxel", "bf16"), ov_t, dv_t,
-                    rgb16, torch.empty(n_v, device="cuda"), torch.empty(n_v, device="cuda"), workspace=ws)
-        torch.cuda.synchronize()
-        rng = np.random.default_rng(2022)
-        idx = np.sort(rng.choice(n_v, args.psnr_rays, replace=False))
-        t1 = time.time()
-        oc = Octree(sc.leaf_ijk, sc.depth)
-        log(f"oracle octree built ({time.time() - t1:.1f}s)")
-        hits = oracle_trace(oc, o_v[idx], d_v[idx], w.K)
-        er, _, _, _ = oracle_render(oc, F, p, w.widths, o_v[idx], d_v[idx], hits)
-        got = rgb16.cpu().numpy()[idx]
-        mse = float(np.mean((got.astype(np.float64) - er) ** 2))
-        psnr = float("inf") if mse == 0 else -10.0 * np.log10(mse)
-        log(f"PSNR bf16 render vs FP64 oracle on {args.psnr_rays} rays: {psnr:.2f} dB")
-        res["oracle_octree"] = oc
+    small = bench_small(torch, svlf, timer, args) if "small" in sections else None
+
+    psnr = bench_psnr(torch, svlf, args, w, sc, F, p, ob_t, db_t, rgb_tt, dep_tt) if "psnr" in sections else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, sc, F, p, ob, db, rgb_t, dep_t, args.cpu_rays, res.get("oracle_octree"))
+        cpu = cpu_baseline(args, ob, db, rgb_t, dep_t)
 
     # roofline of the dominant kernel (the fused shading kernel of the BF16
     # train step): algorithmic bytes per launch over its event-timed duration
@@ -326,8 +320,11 @@ def main():
         achieved = bytes_launch / (sh_ms * 1e-3) / 1e9
         traffic = (MEASURED_TRAFFIC["bytes"] if shade_source_prefix() == MEASURED_TRAFFIC["shade_src_sha256_prefix"]
                    else None)
+        copy = res.get("copy_gbs")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "achievable_copy_gbs": round(copy, 1) if copy else None,
+                "frac_of_copy": round(achieved / copy, 4) if copy else None,
                 "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                 "kernel": "k_shade<bf16,32,64,3,train> + k_reduce",
                 "bytes_per_launch": int(bytes_launch),
@@ -367,8 +364,10 @@ def main():
         "train_bf16_deterministic_rays_per_s": round(n_b / (res["train_bf16_det_ms"] * 1e-3), 1)
         if "train_bf16_det_ms" in res else None,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()} or None,
-        "psnr_bf16_render_vs_fp64_oracle_db": round(psnr, 3) if psnr is not None else None,
+        "psnr_bf16_render_vs_fp64_oracle_db": psnr["bf16_render_vs_fp64_oracle_db"] if psnr else None,
+        "psnr": psnr,
         "device_copy_gbs": round(res["copy_gbs"], 1) if "copy_gbs" in res else None,
+        "other_workloads": small,
         "multi_scene": multi,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -437,34 +436,254 @@ def bench_multi(torch, svlf, timer, args):
     return res
 
 
-def cpu_baseline(w, sc, F, p, ob, db, rgb_t, dep_t, n_rays, oc=None):
-    """The FP64 oracle (trace + render + loss + hand-written backward) on a
-    seeded sample of the training batch, timed on the host."""
+def bench_small(torch, svlf, timer, args):
+    """The workloads that fit in cache: forward views of the depth-4 shell
+    (64x64, K = 4, decoder 8-32-32-4) and of the depth-7 twelve-ellipsoid
+    scene (800x800, K = 8, decoder 16-64-64-64-4), and the training pass on
+    the depth-7 scene with a 2^18-ray batch from 50 views (FP32, the
+    workload's precision, and BF16)."""
+    from synth.configs import get_config
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    out = {}
+    ws = svlf.Workspace()
+    for i in (0, 1):
+        w = get_config(i)
+        sc = w.scene()
+        scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features(), bf16=True)
+        params = T(w.params())
+        o, d = w.view_rays(0)
+        n = o.shape[0]
+        ot, dt = T(o), T(d)
+        bufs = (torch.empty((n, 3), device="cuda"), torch.empty(n, device="cuda"), torch.empty(n, device="cuda"))
+        _, _, _, cnt = svlf.trace_hits(scene.octree, ot, dt, w.K)
+        r = {"workload": w.description, "rays": n, "leaves": int(sc.leaf_ijk.shape[0]),
+             "hits_per_ray": round(float(cnt.sum().item()) / n, 4)}
+        for prec in ("fp32", "bf16"):
+            opts = svlf.make_opts(w.K, "voxel", prec)
+            ms, _ = timer.run(lambda: svlf.render([scene], [n], params, w.widths, opts, ot, dt, *bufs,
+                                                  workspace=ws), args.steps, args.warmup)
+            r[f"fwd_{prec}_ms"] = round(ms / args.steps, 4)
+            r[f"fwd_{prec}_rays_per_s"] = round(n / (ms / args.steps * 1e-3), 1)
+        log(f"workload {i} forward: fp32 {r['fwd_fp32_rays_per_s'] / 1e6:.1f} M rays/s, "
+            f"bf16 {r['fwd_bf16_rays_per_s'] / 1e6:.1f} M rays/s ({n} rays)")
+        out[f"cfg{i}"] = r
+    w = get_config(2)
+    sc = w.scene()
+    scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features(), bf16=True)
+    params = T(w.params())
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
+    n = ob.shape[0]
+    args_t = [T(ob), T(db), T(rgb_t), T(dep_t)]
+    gF = torch.zeros_like(scene.features)
+    gp = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    r = {"workload": w.description, "rays": n}
+    for prec in ("fp32", "bf16"):
+        opts = svlf.make_opts(w.K, "voxel", prec)
+        ms, _ = timer.run(lambda: svlf.train_step([scene], [n], params, w.widths, opts, *args_t, 0.1, 1.0 / n,
+                                                  [gF], gp, loss_out=loss, workspace=ws),
+                          args.steps, args.warmup)
+        r[f"train_{prec}_ms"] = round(ms / args.steps, 4)
+        r[f"train_{prec}_rays_per_s"] = round(n / (ms / args.steps * 1e-3), 1)
+    log(f"workload 2 train step: fp32 {r['train_fp32_rays_per_s'] / 1e6:.1f} M rays/s, "
+        f"bf16 {r['train_bf16_rays_per_s'] / 1e6:.1f} M rays/s")
+    out["cfg2"] = r
+    return out
+
+
+def bench_psnr(torch, svlf, args, w, sc, F, p, ob_t, db_t, rgb_tt, dep_tt):
+    """Networks trained on the batch (args.train_steps steps of the train
+    pass + Adam, features at lr 1e-2, decoder at 1e-3) from the same initial
+    values with the BF16 and with the FP32 decoder.  Reported: PSNR of the
+    BF16-trained network's BF16 render (and of its FP32 render) against the
+    FP64 oracle on 16,384 seeded rays of a view, the mean opacity of those
+    rays that hit the scene, and the held-out PSNR (against the analytic
+    targets, 2^16 seeded pixels of a held-out view) of both trained
+    networks."""
     from oracle.octree import Octree
+    from oracle.render import render as oracle_render
+    from oracle.trace import trace_hits as oracle_trace
+    from paper_2205_07058_amd.train import Trainer
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    hv = w.heldout_views()[0]
+    oh, dh = w.view_rays(hv)
+    sel = np.sort(np.random.default_rng(hv).choice(oh.shape[0], 1 << 16, replace=False))
+    oh, dh = oh[sel], dh[sel]
+    th, _ = w.targets(oh, dh)
+    oht, dht = T(oh), T(dh)
+    trained = {}
+    t0 = time.time()
+    for prec in ("bf16", "fp32"):
+        scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+        tr = Trainer(scene, T(p.copy()), w.widths, w.K, precision=prec, lr_features=1e-2, lr_params=1e-3)
+        for _ in range(args.train_steps):
+            tr.step(ob_t, db_t, rgb_tt, dep_tt)
+        rgb, _, _ = tr.render(oht, dht)
+        torch.cuda.synchronize()
+        mse = float(np.mean((rgb.cpu().numpy().astype(np.float64) - th) ** 2))
+        trained[prec] = (tr, -10.0 * np.log10(mse), float(tr.loss.item()))
+    log(f"trained {args.train_steps} steps per precision ({time.time() - t0:.1f}s): held-out PSNR "
+        f"bf16 {trained['bf16'][1]:.3f} dB, fp32 {trained['fp32'][1]:.3f} dB")
+    tr = trained["bf16"][0]
+    o_v, d_v = w.view_rays(0)
+    idx = np.sort(np.random.default_rng(2022).choice(o_v.shape[0], args.psnr_rays, replace=False))
+    ot, dt = T(o_v[idx]), T(d_v[idx])
+    outs = {}
+    for prec in ("bf16", "fp32"):
+        rgb, _, acc = svlf.render([tr.scene], [idx.size], tr.params, w.widths, svlf.make_opts(w.K, "voxel", prec),
+                                  ot, dt)
+        torch.cuda.synchronize()
+        outs[prec] = (rgb.cpu().numpy(), acc.cpu().numpy())
+    Ft = tr.scene.features.cpu().numpy()
+    pt = tr.params.cpu().numpy()
+    t1 = time.time()
+    oc = Octree(sc.leaf_ijk, sc.depth)
+    hits = oracle_trace(oc, o_v[idx], d_v[idx], w.K)
+    er, _, ea, _ = oracle_render(oc, Ft, pt, w.widths, o_v[idx], d_v[idx], hits)
+    log(f"oracle render of the trained network on {idx.size} rays ({time.time() - t1:.1f}s)")
+    ps = {}
+    for prec in ("bf16", "fp32"):
+        mse = float(np.mean((outs[prec][0].astype(np.float64) - er) ** 2))
+        ps[prec] = float("inf") if mse == 0 else -10.0 * np.log10(mse)
+    hit = hits[3] > 0
+    res = {"steps": args.train_steps,
+           "bf16_render_vs_fp64_oracle_db": round(ps["bf16"], 3),
+           "fp32_render_vs_fp64_oracle_db": round(ps["fp32"], 3),
+           "rays": int(idx.size), "mean_acc_of_hit_rays": round(float(ea[hit].mean()), 4),
+           "rms_rgb": round(float(np.sqrt(np.mean(er ** 2))), 4),
+           "heldout_psnr_bf16_trained_db": round(trained["bf16"][1], 3),
+           "heldout_psnr_fp32_trained_db": round(trained["fp32"][1], 3),
+           "heldout_gap_fp32_minus_bf16_db": round(trained["fp32"][1] - trained["bf16"][1], 3),
+           "final_loss_bf16": round(trained["bf16"][2], 6), "final_loss_fp32": round(trained["fp32"][2], 6)}
+    log(f"trained network: BF16 render vs FP64 oracle {ps['bf16']:.2f} dB, FP32 render {ps['fp32']:.2f} dB, "
+        f"mean opacity of hit rays {res['mean_acc_of_hit_rays']:.3f}")
+    return res
+
+
+def _cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(args, ob, db, rgb_t, dep_t):
+    """The FP64 oracle timed on the host: run in a child process (started
+    before it touches anything but numpy, with one BLAS thread per process)
+    that spreads the work over a process pool on the usable host cores."""
+    import subprocess
+    import tempfile
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(ob.shape[0], args.cpu_rays, replace=False))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "sample.npz")
+        np.savez(path, o=ob[idx], d=db[idx], rgb_t=rgb_t[idx], dep_t=dep_t[idx])
+        env = dict(os.environ)
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[k] = "1"
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", path], env=env,
+                           capture_output=True, text=True)
+    sys.stderr.write(r.stderr)
+    if r.returncode != 0:
+        log(f"oracle timing failed (exit {r.returncode})")
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+_G = {}
+
+
+def _oracle_chunk(job):
+    """One chunk of the oracle work in a pool process (state inherited)."""
     from oracle.render import loss as oracle_loss, render as oracle_render, render_backward
     from oracle.trace import trace_hits as oracle_trace
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = 1
-    if oc is None:
-        t1 = time.time()
-        oc = Octree(sc.leaf_ijk, sc.depth)
-        log(f"oracle octree built ({time.time() - t1:.1f}s)")
-    rng = np.random.default_rng(7)
-    idx = np.sort(rng.choice(ob.shape[0], n_rays, replace=False))
-    o, d = ob[idx], db[idx]
-    t0 = time.time()
-    hits = oracle_trace(oc, o, d, w.K)
-    rgb, dep, acc, st = oracle_render(oc, F, p, w.widths, o, d, hits)
-    L, g_rgb, g_dep = oracle_loss(rgb, dep, rgb_t[idx], dep_t[idx])
+    kind, lo, hi = job
+    g = _G[kind]
+    o, d = g["o"][lo:hi], g["d"][lo:hi]
+    hits = oracle_trace(g["oc"], o, d, g["K"])
+    rgb, dep, acc, st = oracle_render(g["oc"], g["F"], g["p"], g["widths"], o, d, hits)
+    if kind != "train":
+        return None
+    _, g_rgb, g_dep = oracle_loss(rgb, dep, g["rgb_t"][lo:hi], g["dep_t"][lo:hi])
     gF, gp = render_backward(st, g_rgb, g_dep)
-    dt = time.time() - t0
-    log(f"oracle train pass on {n_rays} rays: {dt:.2f}s ({n_rays / dt:.0f} rays/s, {threads} threads)")
-    return {"value": round(n_rays / dt, 2), "unit": "rays/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_rays} seeded rays of the 2^20-ray batch: FP64 oracle trace + render + loss + "
-                      f"backward, single process (numpy, BLAS threads = {threads}); octree build excluded"}
+    rows = np.unique(st.corners.ravel())
+    return rows, gF[rows], gp
+
+
+def cpu_child(path):
+    """Child-process half of cpu_baseline: prints one JSON line."""
+    import multiprocessing as mp
+    from oracle.octree import Octree
+    from synth.configs import get_config
+    z = np.load(path)
+    o, d, rgb_t, dep_t = z["o"], z["d"], z["rgb_t"], z["dep_t"]
+    n = o.shape[0]
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 1
+    P = max(1, min(usable, 16))
+    t0 = time.time()
+    w = get_config(3)
+    sc = w.scene()
+    F = w.features().astype(np.float64)
+    _G["train"] = dict(o=o, d=d, rgb_t=rgb_t, dep_t=dep_t, oc=Octree(sc.leaf_ijk, sc.depth), F=F, p=w.params(),
+                       widths=w.widths, K=w.K)
+    fw = {}
+    for i in (0, 1):
+        wi = get_config(i)
+        sci = wi.scene()
+        oi, di = wi.view_rays(0)
+        _G[f"fwd{i}"] = dict(o=oi, d=di, oc=Octree(sci.leaf_ijk, sci.depth), F=wi.features(), p=wi.params(),
+                             widths=wi.widths, K=wi.K)
+        fw[i] = oi.shape[0]
+    ov, dv = w.view_rays(0)
+    sel = np.sort(np.random.default_rng(3).choice(ov.shape[0], 1 << 14, replace=False))
+    _G["fwd3"] = dict(_G["train"], o=ov[sel], d=dv[sel])
+    log(f"oracle set-up ({time.time() - t0:.1f}s); {P} worker processes ({usable} usable cores)")
+
+    def chunks(kind, m, k):
+        step = (m + k - 1) // k
+        return [(kind, lo, min(m, lo + step)) for lo in range(0, m, step)]
+
+    # one process
+    t1 = time.time()
+    _oracle_chunk(("train", 0, 8192))
+    single = 8192 / (time.time() - t1)
+    res = {}
+    with mp.get_context("fork").Pool(P) as pool:
+        pool.map(_oracle_chunk, chunks("fwd0", fw[0], P))          # warm the workers
+        t2 = time.time()
+        parts = pool.map(_oracle_chunk, chunks("train", n, P))
+        gF = np.zeros_like(F)
+        gp = 0.0
+        for rows, g, gpp in parts:
+            gF[rows] += g
+            gp = gp + gpp
+        res["train"] = n / (time.time() - t2)
+        for kind, m in (("fwd0", fw[0]), ("fwd1", fw[1]), ("fwd3", 1 << 14)):
+            t3 = time.time()
+            pool.map(_oracle_chunk, chunks(kind, m, P))
+            res[kind] = m / (time.time() - t3)
+    log(f"oracle train pass on {n} rays with {P} processes: {res['train']:.0f} rays/s "
+        f"(one process: {single:.0f} rays/s); forward: depth-4 view {res['fwd0']:.0f}, depth-7 view "
+        f"{res['fwd1']:.0f}, paper-scale view sample {res['fwd3']:.0f} rays/s")
+    out = {"value": round(res["train"], 2), "unit": "rays/s", "cores": P, "kind": "oracle",
+           "sample": f"{n} seeded rays of the 2^20-ray batch: FP64 oracle trace + render + loss + backward "
+                     f"(feature gradients reduced over the chunks), {P} worker processes with one BLAS "
+                     f"thread each; octree build excluded",
+           "single_process_rays_per_s": round(single, 2),
+           "forward_rays_per_s": {"depth4_view_64x64": round(res["fwd0"], 1),
+                                  "depth7_view_800x800": round(res["fwd1"], 1),
+                                  "paper_scale_view_sample_2^14": round(res["fwd3"], 1)},
+           "nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": _cpu_info()}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
