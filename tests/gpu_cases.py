@@ -6,13 +6,31 @@ Tolerances (FP32 path, derived from the arithmetic):
   elementwise |err| <= 1e-5 |ref| + 1e-6 S, S = 1 (rgb, acc) or max depth.
   FP32 MLP dot products (length <= 64) and FP32 compositing round at ~1e-7
   relative; the mixed bound covers cancellation near sigma ~ 0.
-* gradients (FP32 atomics, order-dependent): features max|err| <= 1e-5 max|g|
-  and elementwise |err| <= 1e-4 |g| + 1e-5 max|g| (an entry sums many
-  contributions whose FP32 rounding is relative to their own magnitudes, so
-  a cancelling entry gets an absolute floor); MLP parameters max|err| <= 1e-4
-  max|g| (their sums run over all hits of the batch).  Gradient parity uses
-  rays with no decoder pre-activation within 1e-4 of a ReLU kink (there FP32
-  and FP64 may legitimately take different one-sided derivatives).
+* gradients: normwise max|err| <= 1e-5 max|g| (features) or 1e-4 max|g|
+  (decoder parameters, whose sums run over every hit of the batch), and
+  per entry |err| <= c 2^-24 M, where M is the oracle's per-hit
+  contribution scale of that entry (the sum over the hits that reach it of
+  |contribution| plus each such hit's largest contribution to the entry's
+  group, render_backward_hit_magnitude).  Every contribution is computed in
+  FP32 along a chain of about a dozen dependent stages (interpolation, the
+  decoder's dot products of length <= 64 forward and backward, Eq. 3 and its
+  suffix sums), so it carries a rounding error of some hundreds of ulps of
+  the hit's largest contribution; the FP32 sum over the entry's hits (atomics
+  in any order, or the per-block MFMA accumulation and the reduction of the
+  decoder gradient) adds at most a few ulps of S per addition.  A sample
+  point's cell coordinates u carry an absolute error of a few ulps of 1
+  (more in the light field, whose surface point moves with eta's error), which
+  moves a corner's weight by at most that error times D_j = sum_a |dw_j/du_a|:
+  for a weight near zero (a point near a face of its cell) that is no small
+  relative error, so the bound adds c_w 2^-24 W, W = the sum over the hits of
+  D_j |dL/dx_h[c]| (render_backward_weight_scale).  Measured on every parity
+  case, the largest (|err| - c_w 2^-24 W) / (2^-24 M) was 72 for the feature
+  entries (c_w = 8) and 1.0 for the decoder entries; C_FEAT = 256 and
+  C_PARAM = 4 leave a margin of 3.5 and 4.  Unlike a floor relative to max|g|, the bound scales with the
+  entry's own contributions, so a small or cancelling entry is checked at its
+  own scale.  Gradient parity uses rays with no decoder pre-activation within
+  1e-4 of a ReLU kink (there FP32 and FP64 may legitimately take different
+  one-sided derivatives).
 BF16 path: compared with the oracle's BF16-rounding mode; hidden activations
 may round differently where FP32 and FP64 accumulations straddle a bfloat16
 rounding boundary (one bfloat16 ulp = 2^-8 relative), so outputs are checked
@@ -23,7 +41,7 @@ is reported as PSNR.
 import numpy as np
 
 from oracle.octree import Octree
-from oracle.render import render as oracle_render
+from oracle.render import render as oracle_render, split_params
 from oracle.trace import trace_hits as oracle_trace
 
 
@@ -45,20 +63,121 @@ def assert_outputs_close(got, exp, S=1.0, name="", rel=1e-5, abs_el=1e-6, abs_nw
     assert not bad.any(), f"{name}: {bad.sum()} elements outside elementwise bound, worst {err[bad].max()}"
 
 
-def assert_grad_close(got, exp, name="", rel_nw=1e-5, rel_el=1e-4, abs_el=1e-5):
+EPS32 = 2.0 ** -24
+BF16_ULP = 2.0 ** -8
+C_FEAT = 2.0 ** 8
+C_PARAM = 4.0
+C_W = 8.0          # single decoder: the midpoint's cell coordinates to a few ulps
+C_W_LF = 64.0      # light field: the surface point moves with eta's error
+
+
+def grad_error_ratio(got, exp, mag, unit=EPS32, wmag=None, c_w=C_W):
+    """Largest (|got - exp| - 2^-24 c_w W) / (unit M) over the entries with
+    M > 0 (W = the weight-sensitivity scale, 0 if not given), and the largest
+    |got - exp| where M = W = 0 (no contribution: must be exact)."""
+    got = np.asarray(got, np.float64)
+    exp = np.asarray(exp, np.float64)
+    mag = np.asarray(mag, np.float64)
+    assert got.shape == exp.shape == mag.shape
+    err = np.abs(got - exp)
+    if wmag is not None:
+        wmag = np.asarray(wmag, np.float64)
+        assert wmag.shape == mag.shape
+        err_m = err - EPS32 * c_w * wmag
+        pos = (mag > 0) | (wmag > 0)
+    else:
+        err_m = err
+        pos = mag > 0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(mag[pos] > 0, err_m[pos] / (unit * mag[pos]), np.where(err_m[pos] > 0, np.inf, 0.0))
+    return float(np.max(r, initial=0.0)), float(np.max(err[~pos], initial=0.0))
+
+
+def assert_grad_close(got, exp, name="", rel_nw=1e-5, mag=None, c=C_FEAT, unit=EPS32, wmag=None, c_w=C_W):
+    """Normwise max|err| <= rel_nw max|exp|; with ``mag`` (the oracle's
+    per-entry contribution scale M) and ``wmag`` (its weight-sensitivity
+    scale W) also |err| <= c unit M + c_w 2^-24 W for every entry."""
     got = np.asarray(got, np.float64)
     exp = np.asarray(exp, np.float64)
     m = np.abs(exp).max() if exp.size else 0.0
     err = np.abs(got - exp)
     assert np.all(np.isfinite(got)), f"{name}: non-finite gradient"
-    nbad = int(np.sum(err > rel_nw * m))
-    assert err.max(initial=0.0) <= rel_nw * m + 1e-30, \
-        f"{name}: normwise {err.max()} vs {rel_nw * m} ({nbad} of {err.size} entries above)"
-    if rel_el is not None:
-        lim = rel_el * np.abs(exp) + abs_el * m
-        bad = err > lim
-        assert not bad.any(), \
-            f"{name}: {bad.sum()} elements outside elementwise bound (worst ratio {np.max(err / lim):.3g})"
+    if rel_nw is not None:
+        nbad = int(np.sum(err > rel_nw * m))
+        assert err.max(initial=0.0) <= rel_nw * m + 1e-30, \
+            f"{name}: normwise {err.max()} vs {rel_nw * m} ({nbad} of {err.size} entries above)"
+    if mag is not None:
+        worst, at_zero = grad_error_ratio(got, exp, mag, unit, wmag, c_w)
+        print(f"{name}: max (|err| - c_w 2^-24 W) / (unit M) = {worst:.4g} (bound {c:g})")
+        assert at_zero == 0.0, f"{name}: entry without contributions differs by {at_zero}"
+        assert worst <= c, f"{name}: per-entry error {worst:.4g} x unit x M exceeds {c:g}"
+
+
+def residual_terms(g, value, target):
+    """The gradient of a squared residual, g = k (value - target), taken at
+    the size of its terms: k (|value| + |target|).  Another evaluation of the
+    value (FP32 against FP64) moves g by a rounding error of the value, which
+    relative to g is large where value and target nearly cancel; a bound's
+    scale computed from these upstream sizes covers that.  0 where the
+    residual is exactly zero (there both evaluations give 0)."""
+    g = np.asarray(g, np.float64)
+    v = np.asarray(value, np.float64)
+    t = np.asarray(target, np.float64)
+    r = v - t
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(r != 0, np.abs(g) * (np.abs(v) + np.abs(t)) / np.abs(r), 0.0)
+
+
+def loss_scales(mag_fn, weight_fn, st, g_rgb, G_rgb, *rest, **kw):
+    """Contribution and weight-sensitivity scales of a train step's gradient:
+    the oracle's scales at the loss gradient plus those at the size of the
+    loss terms (residual_terms), so that both the chain's own cancellations
+    and the rounding of a nearly cancelling residual are covered.  Returns
+    (M_features, M_params, W)."""
+    mF, mp = mag_fn(st, g_rgb, *rest, **kw)
+    mF2, mp2 = mag_fn(st, G_rgb, *rest, **kw)
+    return mF + mF2, mp + mp2, weight_fn(st, g_rgb, *rest, **kw) + weight_fn(st, G_rgb, *rest, **kw)
+
+
+def cosine(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+# A pre-activation counts as at a kink when it lies within KINK_REL of the
+# scale sum_k |W_ik a_k| + |b_i| of its dot product: FP32 evaluates a dot
+# product of length <= 128 to within about 2^-17 of that scale, and the
+# layer inputs carry errors of the same order from the layers before.
+KINK_REL = 2.0 ** -16
+
+
+def _dot_scales(layers, acts):
+    return [np.abs(a) @ np.abs(W).T + np.abs(b) for (W, b), a in zip(layers, acts)]
+
+
+def decoder_kinks(st):
+    """Hits (of an oracle render state) with a decoder pre-activation at a
+    kink: a hidden ReLU input or the sigma ReLU input within KINK_REL of its
+    dot product's scale."""
+    sc = _dot_scales(split_params(st.params, st.widths), st.acts)
+    near = np.abs(st.out[:, 3]) < KINK_REL * sc[-1][:, 3]
+    for z, s in zip(st.pres, sc[:-1]):
+        near |= np.any(np.abs(z) < KINK_REL * s, axis=1)
+    return near
+
+
+def lf_kinks(st):
+    """As decoder_kinks for the light-field state: both decoders' ReLUs, the
+    tau ReLU, and the clamp of the surface point's cell coordinates."""
+    scT, scC = _dot_scales(st.lt, st.actsT), _dot_scales(st.lc, st.actsC)
+    near = np.abs(st.oT[:, 0]) < KINK_REL * scT[-1][:, 0]
+    for z, s in list(zip(st.presT, scT[:-1])) + list(zip(st.presC, scC[:-1])):
+        near |= np.any(np.abs(z) < KINK_REL * s, axis=1)
+    # the clamp of the surface point's cell coordinates (evaluated to a few
+    # ulps of the result)
+    near |= np.any((np.abs(st.us_raw) < KINK_REL) | (np.abs(st.us_raw - 1.0) < KINK_REL), axis=1)
+    return near
 
 
 def psnr(a, b):

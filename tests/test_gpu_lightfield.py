@@ -6,9 +6,10 @@ oracle, forward and backward, FP32 and BF16."""
 import numpy as np
 import pytest
 
-from oracle.lightfield import render_lf_backward
+from oracle.lightfield import render_lf_backward, render_lf_backward_hit_magnitude, render_lf_backward_weight_scale
 from oracle.render import loss as oracle_loss
-from tests.gpu_cases import LfCase, assert_grad_close, assert_outputs_close, psnr
+from tests.gpu_cases import (C_PARAM, C_W_LF, LfCase, assert_grad_close, assert_outputs_close, psnr,
+                             loss_scales, residual_terms)
 from tests.helpers import random_rays
 
 pytestmark = pytest.mark.gpu
@@ -61,11 +62,13 @@ def test_lf_backward_fp32(gpu_lib):
         gF, gp = case.gpu_backward(o, d, g_rgb, g_dep, g_acc)
         _, _, _, st = case.oracle(o, d)
         eF, ep = render_lf_backward(st, g_rgb, g_dep, g_acc)
+        mF, mp = render_lf_backward_hit_magnitude(st, g_rgb, g_dep, g_acc)
+        mW = render_lf_backward_weight_scale(st, g_rgb, g_dep, g_acc)
         ct = case.dec[0]
         assert np.abs(eF[:, :ct]).max() > 0 and np.abs(eF[:, ct:]).max() > 0, name
-        assert_grad_close(gF[:, :ct], eF[:, :ct], f"{name} grad Z_T")
-        assert_grad_close(gF[:, ct:], eF[:, ct:], f"{name} grad Z_C")
-        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(gF[:, :ct], eF[:, :ct], f"{name} grad Z_T", mag=mF[:, :ct], wmag=mW[:, :ct], c_w=C_W_LF)
+        assert_grad_close(gF[:, ct:], eF[:, ct:], f"{name} grad Z_C", mag=mF[:, ct:], wmag=mW[:, ct:], c_w=C_W_LF)
+        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
 
 
 def test_lf_train_step_fp32(gpu_lib):
@@ -91,11 +94,13 @@ def test_lf_train_step_fp32(gpu_lib):
         er, ed, _, st = case.oracle(o, d)
         L, g_rgb, g_dep = oracle_loss(er, ed, t_rgb, t_dep, 0.1)
         eF, ep = render_lf_backward(st, g_rgb, g_dep)
+        mF, mp, mW = loss_scales(render_lf_backward_hit_magnitude, render_lf_backward_weight_scale, st,
+                                 g_rgb, residual_terms(g_rgb, er, t_rgb), g_dep)
         assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L), name
         assert_outputs_close(out_rgb.cpu().numpy(), er, 1.0, f"{name} train rgb")
         assert_outputs_close(out_dep.cpu().numpy(), ed, max(1.0, np.abs(ed).max()), f"{name} train depth")
-        assert_grad_close(case.rows(gF), eF, f"{name} train grad_features")
-        assert_grad_close(gp.cpu().numpy(), ep, f"{name} train grad_params", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(case.rows(gF), eF, f"{name} train grad_features", mag=mF, wmag=mW, c_w=C_W_LF)
+        assert_grad_close(gp.cpu().numpy(), ep, f"{name} train grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
 
 
 def test_lf_backward_bf16(gpu_lib):
@@ -153,6 +158,15 @@ def test_lf_train_stage_fp32(gpu_lib, kind, freeze):
     rgb, _, _, st = case.oracle(o, d)
     L, g_rgb, hg = stage_loss(st, hits, rgb, t_rgb, t_d, kind, lam_eta, lam_tau, ls)
     eF, ep = render_lf_backward(st, g_rgb, np.zeros(n), hit_grads=hg)
+    # squared residuals taken at the size of their terms: the composited
+    # colour's (volume) and the surface voxel's colour (surface)
+    G_rgb = residual_terms(g_rgb, rgb, t_rgb)
+    hG = (residual_terms(hg[0], st.c, t_rgb[st.ray_i]), hg[1], hg[2])
+    mF, mp = render_lf_backward_hit_magnitude(st, g_rgb, np.zeros(n), hit_grads=hg)
+    mF2, mp2 = render_lf_backward_hit_magnitude(st, G_rgb, np.zeros(n), hit_grads=hG)
+    mF, mp = mF + mF2, mp + mp2
+    mW = (render_lf_backward_weight_scale(st, g_rgb, np.zeros(n), hit_grads=hg)
+          + render_lf_backward_weight_scale(st, G_rgb, np.zeros(n), hit_grads=hG))
     assert np.count_nonzero(hg[1]) > 100
     assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L)
     ct = case.dec[0]
@@ -160,13 +174,13 @@ def test_lf_train_stage_fp32(gpu_lib, kind, freeze):
     wt, _ = widths_of(case.dec)
     nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
     gFr, gpn = case.rows(gF), gp.cpu().numpy()
-    assert_grad_close(gFr[:, :ct], eF[:, :ct], f"{kind} grad Z_T")
-    assert_grad_close(gpn[:nt], ep[:nt], f"{kind} grad F_T", rel_nw=1e-4, rel_el=None)
+    assert_grad_close(gFr[:, :ct], eF[:, :ct], f"{kind} grad Z_T", mag=mF[:, :ct], wmag=mW[:, :ct], c_w=C_W_LF)
+    assert_grad_close(gpn[:nt], ep[:nt], f"{kind} grad F_T", rel_nw=1e-4, mag=mp[:nt], c=C_PARAM)
     if freeze:
         assert np.all(gFr[:, ct:] == 0) and np.all(gpn[nt:] == 0)
     else:
-        assert_grad_close(gFr[:, ct:], eF[:, ct:], f"{kind} grad Z_C")
-        assert_grad_close(gpn[nt:], ep[nt:], f"{kind} grad F_C", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(gFr[:, ct:], eF[:, ct:], f"{kind} grad Z_C", mag=mF[:, ct:], wmag=mW[:, ct:], c_w=C_W_LF)
+        assert_grad_close(gpn[nt:], ep[nt:], f"{kind} grad F_C", rel_nw=1e-4, mag=mp[nt:], c=C_PARAM)
 
 
 def test_lf_staged_training(gpu_lib):

@@ -7,10 +7,15 @@ import numpy as np
 import pytest
 
 from oracle.octree import Octree
-from oracle.render import loss as oracle_loss, render as oracle_render
+from oracle.render import (loss as oracle_loss, render as oracle_render, render_backward,
+                           render_backward_hit_magnitude,
+                           render_backward_weight_scale)
 from oracle.trace import trace_hits as oracle_trace
 from synth.configs import get_config
-from tests.gpu_cases import assert_outputs_close, psnr
+from tests.gpu_cases import (BF16_ULP, C_PARAM, C_W, C_W_LF, EPS32, assert_grad_close, assert_outputs_close,
+                             cosine, decoder_kinks as _decoder_kinks, lf_kinks as _lf_kinks, loss_scales,
+                             residual_terms,
+                             psnr)
 
 pytestmark = pytest.mark.gpu
 
@@ -257,3 +262,206 @@ def test_lightfield_train_step_full_batch_equals_chunked_calls(gpu_lib, paper, p
     sf, sp = np.abs(fb).max(), np.abs(pb).max()
     assert sf > 0 and np.abs(fa - fb).max() <= 1e-4 * sf
     assert sp > 0 and np.abs(pa - pb).max() <= 1e-4 * sp
+
+
+# ---------------------------------------------------------------------------
+# Gradient parity at the size the benchmarked kernels run.  A subset of
+# N_SUB rays of the 2^20-ray batch spans four full groups of 256 work items
+# (65,536 rays, whose rays the shading kernels interleave) and a ragged tail;
+# the persistent grid then runs several items per block, and each window's
+# feature-gradient scatter is deferred behind the next window's gather and
+# across items.  The rays are those away from every kink of the loss: no
+# decoder pre-activation within 1e-4 of zero (FP32 and FP64 may take
+# different one-sided derivatives there) and a depth residual of the L1 term
+# clear of zero by more than the precision's output error.
+
+N_SUB = 4 * 65536 + 777
+def _batch(paper):
+    if "batch" not in paper:
+        w = paper["w"]
+        paper["batch"] = w.train_batch(w.batch, step=0)
+    return paper["batch"]
+
+
+def _kink_free_subset(paper, render_fn, kinks, bf16, seed):
+    """First N_SUB rays (in batch order) of a seeded sample of the batch that
+    avoid every kink; returns (o, d, rgb*, depth*, hit lists) of those rays."""
+    w = paper["w"]
+    ob, db, rgb_t, dep_t = _batch(paper)
+    idx = np.sort(np.random.default_rng(seed).choice(ob.shape[0], N_SUB + N_SUB // 4, replace=False))
+    hits = oracle_trace(paper["oc"], ob[idx], db[idx], w.K)
+    _, dep, _, st = render_fn(ob[idx], db[idx], hits, bf16)
+    bad = np.zeros(idx.size, bool)
+    bad[np.unique(st.ray_i[kinks(st)])] = True
+    print(f"kink-free subset: {np.count_nonzero(bad)} of {idx.size} sampled rays excluded, "
+          f"{st.ray_i.size} hits sampled")
+    margin = (2.0 ** -6 if bf16 else 1e-4) * np.maximum(1.0, np.abs(dep_t[idx]))
+    res = dep - dep_t[idx]
+    bad |= (res != 0) & (np.abs(res) < margin)
+    keep = np.nonzero(~bad)[0][:N_SUB]
+    assert keep.size == N_SUB
+    sel = idx[keep]
+    return ob[sel], db[sel], rgb_t[sel], dep_t[sel], tuple(x[keep] for x in hits)
+
+
+def _gpu_train(gpu_lib, scene, params, opts, o, d, rgb_t, dep_t, lf=False):
+    import torch
+    n = o.shape[0]
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    gF = torch.zeros_like(scene.features)
+    gp = torch.zeros_like(params)
+    loss = torch.zeros(1, device="cuda")
+    out_rgb = torch.empty((n, 3), device="cuda")
+    out_dep = torch.empty(n, device="cuda")
+    step = gpu_lib.lf_train_step if lf else gpu_lib.train_step
+    extra = () if lf else (paper_widths(),)
+    step([scene], [n], params, *extra, opts, T(o), T(d), T(rgb_t), T(dep_t), 0.1, 1.0 / n,
+         [gF], gp, out_rgb=out_rgb, out_depth=out_dep, loss_out=loss)
+    torch.cuda.synchronize()
+    return (gF.cpu().numpy(), gp.cpu().numpy(), out_rgb.cpu().numpy(), out_dep.cpu().numpy(),
+            float(loss.item()))
+
+
+def paper_widths():
+    return tuple(get_config(3).widths)
+
+
+def _check_bf16_grads(got, exp, mag, name, wmag=None, c_w=C_W):
+    """BF16 against the oracle's BF16-rounding mode: where an FP32 and an FP64
+    value straddle a bfloat16 rounding boundary the two round apart by one
+    bfloat16 ulp, and the decoder's chain amplifies such a step like any
+    rounding error, so the comparison is by direction and size of the whole
+    gradient (cosine, relative L2); the per-entry error in units of 2^-8 M
+    is reported as quantiles."""
+    c = cosine(got, exp)
+    r = float(np.linalg.norm(got - exp) / np.linalg.norm(exp))
+    err = np.abs(np.asarray(got, np.float64) - exp)
+    if wmag is not None:
+        err = np.maximum(err - EPS32 * c_w * wmag, 0.0)
+    pos = mag > 0
+    q = np.quantile(err[pos] / (BF16_ULP * mag[pos]), [0.5, 0.99, 0.999, 1.0])
+    print(f"{name}: cosine {c:.8f}, relative L2 {r:.3g}, |err| / (2^-8 M) quantiles 50/99/99.9/100%: "
+          f"{q[0]:.3g} {q[1]:.3g} {q[2]:.3g} {q[3]:.3g}")
+    assert c >= 0.99999 and r <= 2e-3, (name, c, r)
+    assert np.all(err[~pos] == 0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_train_step_gradients_on_batch_subset(gpu_lib, paper, precision):
+    """svlf_train_step on N_SUB rays of the paper-scale batch: loss, outputs
+    and both gradients against the oracle (FP32: per-entry bounds; BF16:
+    against the oracle's BF16-rounding mode)."""
+    w = paper["w"]
+    bf = precision == "bf16"
+    F, p = paper["F"], paper["p"]
+    rnd = lambda o, d, hits, b: oracle_render(paper["oc"], F, p, w.widths, o, d, hits, bf16=b)
+    o, d, rgb_t, dep_t, hits = _kink_free_subset(paper, rnd, _decoder_kinks, bf, 11)
+    gF, gp, r, dd, L = _gpu_train(gpu_lib, paper["scene"], paper["params"],
+                                  gpu_lib.make_opts(w.K, "voxel", precision), o, d, rgb_t, dep_t)
+    er, ed, _, st = rnd(o, d, hits, bf)
+    L_ref, g_rgb, g_dep = oracle_loss(er, ed, rgb_t, dep_t, 0.1)
+    eF, ep = render_backward(st, g_rgb, g_dep)
+    mF, mp, mW = loss_scales(render_backward_hit_magnitude, render_backward_weight_scale, st, g_rgb,
+                             residual_terms(g_rgb, er, rgb_t), g_dep)
+    print(f"{precision}: {o.shape[0]} rays, {st.ray_i.size} hits, {np.count_nonzero(mF.any(axis=1))} "
+          f"feature rows reached")
+    if not bf:
+        assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
+        assert_outputs_close(r, er, 1.0, "rgb")
+        assert_outputs_close(dd, ed, max(1.0, np.abs(ed).max()), "depth")
+        assert_grad_close(gF, eF, "grad_features", mag=mF, wmag=mW)
+        assert_grad_close(gp, ep, "grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+    else:
+        assert abs(L - L_ref) <= 2 ** -8 * abs(L_ref)
+        assert np.abs(r - er).max() <= 2 ** -6 * np.abs(er).max() + 1e-4
+        _check_bf16_grads(gF, eF, mF, "bf16 grad_features", mW)
+        _check_bf16_grads(gp, ep, mp, "bf16 grad_params")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_render_backward_full_batch_sparse_upstream(gpu_lib, paper, precision):
+    """svlf_render_backward on the whole 2^20-ray batch with upstream
+    gradients that vanish except on 2,048 seeded kink-free rays: the kernel
+    takes every full-size path (interleaved groups, several items per block,
+    scatter deferred across items) while the oracle needs the sampled rays
+    only (a ray with zero upstream gradient contributes exact zeros)."""
+    import torch
+    w = paper["w"]
+    bf = precision == "bf16"
+    ob, db, _, _ = _batch(paper)
+    n = ob.shape[0]
+    idx = _sample(n, 2600, 12)
+    hits = oracle_trace(paper["oc"], ob[idx], db[idx], w.K)
+    _, _, _, st = oracle_render(paper["oc"], paper["F"], paper["p"], w.widths, ob[idx], db[idx], hits, bf16=bf)
+    bad = np.zeros(idx.size, bool)
+    bad[np.unique(st.ray_i[_decoder_kinks(st)])] = True
+    sel = idx[~bad][:2048]
+    rng = np.random.default_rng(13)
+    g_rgb = np.zeros((n, 3), np.float32)
+    g_dep = np.zeros(n, np.float32)
+    g_acc = np.zeros(n, np.float32)
+    g_rgb[sel] = rng.normal(size=(sel.size, 3))
+    g_dep[sel] = rng.normal(size=sel.size) * 0.1
+    g_acc[sel] = rng.normal(size=sel.size)
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    gF = torch.zeros_like(paper["scene"].features)
+    gp = torch.zeros_like(paper["params"])
+    gpu_lib.render_backward([paper["scene"]], [n], paper["params"], w.widths,
+                            gpu_lib.make_opts(w.K, "voxel", precision), T(ob), T(db), T(g_rgb), T(g_dep),
+                            T(g_acc), [gF], gp)
+    torch.cuda.synchronize()
+    gF, gp = gF.cpu().numpy(), gp.cpu().numpy()
+    hs = oracle_trace(paper["oc"], ob[sel], db[sel], w.K)
+    _, _, _, st = oracle_render(paper["oc"], paper["F"], paper["p"], w.widths, ob[sel], db[sel], hs, bf16=bf)
+    ups = (g_rgb[sel], g_dep[sel], g_acc[sel])
+    eF, ep = render_backward(st, *ups)
+    mF, mp = render_backward_hit_magnitude(st, *ups)
+    mW = render_backward_weight_scale(st, *ups)
+    assert st.ray_i.size > 1000
+    if not bf:
+        assert_grad_close(gF, eF, "sparse-upstream grad_features", mag=mF, wmag=mW)
+        assert_grad_close(gp, ep, "sparse-upstream grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+    else:
+        _check_bf16_grads(gF, eF, mF, "sparse-upstream bf16 grad_features", mW)
+        _check_bf16_grads(gp, ep, mp, "sparse-upstream bf16 grad_params")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_lightfield_train_step_gradients_on_batch_subset(gpu_lib, paper, precision):
+    """svlf_lf_train_step (the paper's two-decoder function) on N_SUB rays of
+    the paper-scale batch against the light-field oracle."""
+    import torch
+    from oracle.lightfield import (render_lf, render_lf_backward, render_lf_backward_hit_magnitude,
+                                   render_lf_backward_weight_scale)
+    from synth.configs import lf_inputs
+    w, sc = paper["w"], paper["sc"]
+    bf = precision == "bf16"
+    if "lf" not in paper:
+        F, p = lf_inputs(w.seed, sc.n_vertices)
+        paper["lf"] = (F, p, gpu_lib.DeviceScene.lf_from_host(sc.leaf_ijk, sc.depth, F, bf16=True),
+                       torch.from_numpy(p).cuda())
+    F, p, scene, params = paper["lf"]
+    dec = tuple(gpu_lib.LF_DECODERS)
+    rnd = lambda o, d, hits, b: render_lf(paper["oc"], F, p, dec, o, d, hits, bf16=b)
+    o, d, rgb_t, dep_t, hits = _kink_free_subset(paper, rnd, _lf_kinks, bf, 14)
+    gF, gp, r, dd, L = _gpu_train(gpu_lib, scene, params, gpu_lib.make_opts(w.K, "direct", precision),
+                                  o, d, rgb_t, dep_t, lf=True)
+    gF = gpu_lib.lf_feature_rows(gF, sc.n_vertices)
+    er, ed, _, st = rnd(o, d, hits, bf)
+    L_ref, g_rgb, g_dep = oracle_loss(er, ed, rgb_t, dep_t, 0.1)
+    eF, ep = render_lf_backward(st, g_rgb, g_dep)
+    mF, mp, mW = loss_scales(render_lf_backward_hit_magnitude, render_lf_backward_weight_scale, st, g_rgb,
+                             residual_terms(g_rgb, er, rgb_t), g_dep)
+    ct = dec[0]
+    if not bf:
+        assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
+        assert_outputs_close(r, er, 1.0, "lf rgb")
+        assert_outputs_close(dd, ed, max(1.0, np.abs(ed).max()), "lf depth")
+        assert_grad_close(gF[:, :ct], eF[:, :ct], "lf grad Z_T", mag=mF[:, :ct], wmag=mW[:, :ct], c_w=C_W_LF)
+        assert_grad_close(gF[:, ct:], eF[:, ct:], "lf grad Z_C", mag=mF[:, ct:], wmag=mW[:, ct:], c_w=C_W_LF)
+        assert_grad_close(gp, ep, "lf grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+    else:
+        assert abs(L - L_ref) <= 2 ** -8 * abs(L_ref)
+        assert np.abs(r - er).max() <= 2 ** -6 * np.abs(er).max() + 1e-4
+        _check_bf16_grads(gF, eF, mF, "lf bf16 grad_features", mW, C_W_LF)
+        _check_bf16_grads(gp, ep, mp, "lf bf16 grad_params")

@@ -4,9 +4,12 @@ svlf_train_step against the FP64 oracle (SVLF sections 4.1-4.3, Eq. 3)."""
 import numpy as np
 import pytest
 
-from oracle.render import bf16_round, loss as oracle_loss, mlp_forward as oracle_mlp, render_backward
+from oracle.render import (bf16_round, loss as oracle_loss, mlp_forward as oracle_mlp, render_backward,
+                           render_backward_hit_magnitude,
+                           render_backward_weight_scale)
 from synth.configs import get_config, tiny_workload, xavier_params
-from tests.gpu_cases import Case, assert_grad_close, assert_outputs_close, psnr
+from tests.gpu_cases import (C_PARAM, C_W_LF, Case, assert_grad_close, assert_outputs_close, psnr,
+                             loss_scales, residual_terms)
 from tests.helpers import random_rays
 
 pytestmark = pytest.mark.gpu
@@ -140,9 +143,11 @@ def test_backward_fp32_against_oracle(gpu_lib):
         gF, gp = _gpu_backward(case, o, d, g_rgb, g_dep, g_acc)
         _, _, _, st = case.oracle(o, d)
         eF, ep = render_backward(st, g_rgb, g_dep, g_acc)
+        mF, mp = render_backward_hit_magnitude(st, g_rgb, g_dep, g_acc)
+        mW = render_backward_weight_scale(st, g_rgb, g_dep, g_acc)
         assert np.abs(eF).max() > 0 and np.abs(ep).max() > 0, name
-        assert_grad_close(gF, eF, f"{name} grad_features")
-        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(gF, eF, f"{name} grad_features", mag=mF, wmag=mW)
+        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
         # conservation: trilinear weights sum to one per hit
         assert abs(gF.sum() - eF.sum()) <= 1e-4 * np.abs(eF).sum()
 
@@ -189,10 +194,12 @@ def test_train_step_fp32_against_oracle(gpu_lib):
         er, ed, ea, st = case.oracle(o, d)
         L, g_rgb, g_dep = oracle_loss(er, ed, t_rgb, t_dep, 0.1)
         eF, ep = render_backward(st, g_rgb, g_dep)
+        mF, mp, mW = loss_scales(render_backward_hit_magnitude, render_backward_weight_scale, st, g_rgb,
+                                 residual_terms(g_rgb, er, t_rgb), g_dep)
         assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L), name
         assert_outputs_close(out_rgb.cpu().numpy(), er, 1.0, f"{name} rgb")
-        assert_grad_close(gF.cpu().numpy(), eF, f"{name} grad_features")
-        assert_grad_close(gp.cpu().numpy(), ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(gF.cpu().numpy(), eF, f"{name} grad_features", mag=mF, wmag=mW)
+        assert_grad_close(gp.cpu().numpy(), ep, f"{name} grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
 
 
 def test_backward_bf16_against_bf16_oracle(gpu_lib):
@@ -245,7 +252,7 @@ def test_multi_scene_render_and_backward(gpu_lib):
     torch.cuda.synchronize()
     rgb = rgb.cpu().numpy()
     dep = dep.cpu().numpy()
-    ep_total = 0
+    ep_total = mp_total = 0
     start = 0
     for c, n, gF in zip(cases, counts, gFs):
         sl = slice(start, start + n)
@@ -253,10 +260,13 @@ def test_multi_scene_render_and_backward(gpu_lib):
         assert_outputs_close(rgb[sl], er, 1.0, "multi rgb")
         assert_outputs_close(dep[sl], ed, max(1.0, np.abs(ed).max()), "multi depth")
         eF, ep = render_backward(st, g_rgb[sl], g_dep[sl])
-        assert_grad_close(gF.cpu().numpy(), eF, "multi grad_features")
+        mF, mp = render_backward_hit_magnitude(st, g_rgb[sl], g_dep[sl])
+        mW = render_backward_weight_scale(st, g_rgb[sl], g_dep[sl])
+        assert_grad_close(gF.cpu().numpy(), eF, "multi grad_features", mag=mF, wmag=mW)
         ep_total = ep_total + ep
+        mp_total = mp_total + mp
         start += n
-    assert_grad_close(gp.cpu().numpy(), ep_total, "multi grad_params", rel_nw=1e-4, rel_el=None)
+    assert_grad_close(gp.cpu().numpy(), ep_total, "multi grad_params", rel_nw=1e-4, mag=mp_total, c=C_PARAM)
 
 
 def test_deterministic_feature_gradient(gpu_lib):
@@ -290,8 +300,10 @@ def test_deterministic_feature_gradient(gpu_lib):
         gFa, gpa = run(0)
         _, _, _, st = case.oracle(o, d)
         eF, ep = render_backward(st, g_rgb, g_dep)
-        assert_grad_close(gF1, eF, f"{name} deterministic grad_features")
-        assert_grad_close(gF1, gFa, f"{name} deterministic vs atomic")
+        mF, _ = render_backward_hit_magnitude(st, g_rgb, g_dep)
+        mW = render_backward_weight_scale(st, g_rgb, g_dep)
+        assert_grad_close(gF1, eF, f"{name} deterministic grad_features", mag=mF, wmag=mW)
+        assert_grad_close(gF1, gFa, f"{name} deterministic vs atomic", mag=mF, wmag=mW)
         np.testing.assert_array_equal(gp1, gpa)
 
 
@@ -300,7 +312,7 @@ def test_max_K_solid_scene(gpu_lib):
     hits: windows hold few rays each; forward and backward against the
     oracle, and the light-field path on the same scene."""
     from tests.gpu_cases import LfCase
-    from oracle.lightfield import render_lf_backward
+    from oracle.lightfield import render_lf_backward, render_lf_backward_hit_magnitude, render_lf_backward_weight_scale
     w = tiny_workload(17, 5, 16, (16, 64, 64, 64, 4), 16, n_obj=3)
     case = Case.from_workload(gpu_lib, w, feat_scale=3.0, sigma_bias=0.3)
     rng = np.random.default_rng(5)
@@ -317,8 +329,10 @@ def test_max_K_solid_scene(gpu_lib):
     gF, gp = _gpu_backward(case, o[keep], d[keep], g_rgb, g_dep, None)
     _, _, _, st2 = case.oracle(o[keep], d[keep])
     eF, ep = render_backward(st2, g_rgb, g_dep)
-    assert_grad_close(gF, eF, "K16 grad_features")
-    assert_grad_close(gp, ep, "K16 grad_params", rel_nw=1e-4, rel_el=None)
+    mF, mp = render_backward_hit_magnitude(st2, g_rgb, g_dep)
+    mW = render_backward_weight_scale(st2, g_rgb, g_dep)
+    assert_grad_close(gF, eF, "K16 grad_features", mag=mF, wmag=mW)
+    assert_grad_close(gp, ep, "K16 grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
     lf = LfCase(gpu_lib, w.scene().leaf_ijk, 5,
                 np.random.default_rng(1).normal(0, 0.5, (w.scene().n_vertices, 96)).astype(np.float32),
                 LfCase.random(gpu_lib, 17, 5, K=16).p, 16)
@@ -332,8 +346,10 @@ def test_max_K_solid_scene(gpu_lib):
     lgF, lgp = lf.gpu_backward(o[keep], d[keep], lg_rgb, lg_dep)
     _, _, _, lst2 = lf.oracle(o[keep], d[keep])
     leF, lep = render_lf_backward(lst2, lg_rgb, lg_dep)
-    assert_grad_close(lgF, leF, "K16 lf grad_features")
-    assert_grad_close(lgp, lep, "K16 lf grad_params", rel_nw=1e-4, rel_el=None)
+    lmF, lmp = render_lf_backward_hit_magnitude(lst2, lg_rgb, lg_dep)
+    lmW = render_lf_backward_weight_scale(lst2, lg_rgb, lg_dep)
+    assert_grad_close(lgF, leF, "K16 lf grad_features", mag=lmF, wmag=lmW, c_w=C_W_LF)
+    assert_grad_close(lgp, lep, "K16 lf grad_params", rel_nw=1e-4, mag=lmp, c=C_PARAM)
 
 
 def test_depth_10_scene(gpu_lib):
@@ -392,11 +408,13 @@ def test_depth_10_scene(gpu_lib):
     gF, gp = _gpu_backward(case, o[keep], d[keep], g_rgb, g_dep, None)
     _, _, _, st = case.oracle(o[keep], d[keep])
     eF, ep = render_backward(st, g_rgb, g_dep)
-    assert_grad_close(gF, eF, "depth 10 grad_features")
-    assert_grad_close(gp, ep, "depth 10 grad_params", rel_nw=1e-4, rel_el=None)
+    mF, mp = render_backward_hit_magnitude(st, g_rgb, g_dep)
+    mW = render_backward_weight_scale(st, g_rgb, g_dep)
+    assert_grad_close(gF, eF, "depth 10 grad_features", mag=mF, wmag=mW)
+    assert_grad_close(gp, ep, "depth 10 grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
     # the light-field function on the same scene and rays
     from tests.gpu_cases import LfCase
-    from oracle.lightfield import render_lf_backward
+    from oracle.lightfield import render_lf_backward, render_lf_backward_hit_magnitude, render_lf_backward_weight_scale
     lf = LfCase(gpu_lib, cells, depth, rng.normal(0.0, 0.5, (nv, 96)).astype(np.float32),
                 LfCase.random(gpu_lib, 10, 5, K=8).p, 8)
     lrgb, ldep, lacc = lf.gpu_render(o, d)
@@ -409,5 +427,7 @@ def test_depth_10_scene(gpu_lib):
     lgF, lgp = lf.gpu_backward(o[keep], d[keep], lg_rgb, lg_dep)
     _, _, _, lst = lf.oracle(o[keep], d[keep])
     leF, lep = render_lf_backward(lst, lg_rgb, lg_dep)
-    assert_grad_close(lgF, leF, "depth 10 lf grad_features")
-    assert_grad_close(lgp, lep, "depth 10 lf grad_params", rel_nw=1e-4, rel_el=None)
+    lmF, lmp = render_lf_backward_hit_magnitude(lst, lg_rgb, lg_dep)
+    lmW = render_lf_backward_weight_scale(lst, lg_rgb, lg_dep)
+    assert_grad_close(lgF, leF, "depth 10 lf grad_features", mag=lmF, wmag=lmW, c_w=C_W_LF)
+    assert_grad_close(lgp, lep, "depth 10 lf grad_params", rel_nw=1e-4, mag=lmp, c=C_PARAM)

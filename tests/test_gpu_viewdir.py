@@ -6,9 +6,11 @@ precisions, backward and the fused train step."""
 import numpy as np
 import pytest
 
-from oracle.render import loss as oracle_loss, mlp_forward as oracle_mlp, render_backward
+from oracle.render import (loss as oracle_loss, mlp_forward as oracle_mlp, render_backward,
+                           render_backward_hit_magnitude, render_backward_weight_scale)
 from synth.configs import tiny_workload, xavier_params
-from tests.gpu_cases import Case, assert_grad_close, assert_outputs_close, psnr
+from tests.gpu_cases import (C_PARAM, Case, assert_grad_close, assert_outputs_close, loss_scales, psnr,
+                             residual_terms)
 from tests.helpers import random_rays
 from tests.test_gpu_render import _gpu_backward
 
@@ -76,9 +78,11 @@ def test_backward_and_train_step_viewdir_fp32(gpu_lib):
         gF, gp = _gpu_backward(case, o, d, g_rgb, g_dep, None)
         _, _, _, st = case.oracle(o, d)
         eF, ep = render_backward(st, g_rgb, g_dep)
+        mF, mp = render_backward_hit_magnitude(st, g_rgb, g_dep)
+        mW = render_backward_weight_scale(st, g_rgb, g_dep)
         assert gF.shape == case.F.shape and np.abs(eF).max() > 0
-        assert_grad_close(gF, eF, f"{name} grad_features")
-        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(gF, eF, f"{name} grad_features", mag=mF, wmag=mW)
+        assert_grad_close(gp, ep, f"{name} grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
         # fused train step
         t_rgb = rng.uniform(0, 1, (n, 3)).astype(np.float32)
         t_dep = rng.uniform(0, 5, n).astype(np.float32)
@@ -93,9 +97,11 @@ def test_backward_and_train_step_viewdir_fp32(gpu_lib):
         er, ed, _, st = case.oracle(o, d)
         L, lg_rgb, lg_dep = oracle_loss(er, ed, t_rgb, t_dep, 0.1)
         eF2, ep2 = render_backward(st, lg_rgb, lg_dep)
+        mF2, mp2, mW2 = loss_scales(render_backward_hit_magnitude, render_backward_weight_scale, st, lg_rgb,
+                                    residual_terms(lg_rgb, er, t_rgb), lg_dep)
         assert abs(float(loss_t.item()) - L) <= 1e-5 * abs(L), name
-        assert_grad_close(gF2.cpu().numpy(), eF2, f"{name} train grad_features")
-        assert_grad_close(gp2.cpu().numpy(), ep2, f"{name} train grad_params", rel_nw=1e-4, rel_el=None)
+        assert_grad_close(gF2.cpu().numpy(), eF2, f"{name} train grad_features", mag=mF2, wmag=mW2)
+        assert_grad_close(gp2.cpu().numpy(), ep2, f"{name} train grad_params", rel_nw=1e-4, mag=mp2, c=C_PARAM)
 
 
 def test_viewdir_bf16_backward_close(gpu_lib):

@@ -1,0 +1,343 @@
+"""Parity on the two workloads that are neither a single view nor the
+paper-scale batch:
+
+* the FP32 training step on the depth-7 twelve-ellipsoid scene with a batch
+  of 2^18 rays from 50 views and analytic Lambertian targets (Eq. 3, the loss
+  and its hand-written backward), compared with the oracle over the whole
+  batch, plus directional finite differences of the GPU loss itself;
+* the ragged batch of 8 scenes (octree depths 7, 8, 8, 9, 9, 10, 10, 10,
+  0.5-3% occupancy, 2^16..2^20 rays per scene, C = 32, decoder
+  32-64-64-64-4) rendered and differentiated in one launch per kernel and
+  replayed from a HIP graph, each scene compared with the oracle on seeded
+  rays;
+* BF16-decoder training against FP32-decoder training on the depth-7 scene:
+  the same seeds, batches and steps, held-out PSNR within 0.1 dB.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.octree import Octree
+from oracle.render import (loss as oracle_loss, render as oracle_render, render_backward,
+                           render_backward_hit_magnitude,
+                           render_backward_weight_scale)
+from oracle.trace import trace_hits as oracle_trace
+from synth.configs import get_config, get_multi
+from tests.gpu_cases import (C_PARAM, assert_grad_close, assert_outputs_close, decoder_kinks, psnr,
+                             loss_scales, residual_terms)
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def cfg2(gpu_lib):
+    import torch
+    w = get_config(2)
+    sc = w.scene()
+    F, p = w.features(), w.params()
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
+    scene = gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True)
+    return dict(w=w, sc=sc, F=F, p=p, oc=Octree(sc.leaf_ijk, sc.depth), batch=(ob, db, rgb_t, dep_t),
+                scene=scene, params=torch.from_numpy(p).cuda())
+
+
+def _train_step(gpu_lib, c, precision, params=None, lam=0.1):
+    import torch
+    w = c["w"]
+    ob, db, rgb_t, dep_t = c["batch"]
+    n = ob.shape[0]
+    scene = c["scene"]
+    gF = torch.zeros_like(scene.features)
+    gp = torch.zeros_like(c["params"])
+    loss = torch.zeros(1, device="cuda")
+    out_rgb = torch.empty((n, 3), device="cuda")
+    out_dep = torch.empty(n, device="cuda")
+    gpu_lib.train_step([scene], [n], c["params"] if params is None else params, w.widths,
+                       gpu_lib.make_opts(w.K, "voxel", precision), _t(ob), _t(db), _t(rgb_t), _t(dep_t),
+                       lam, 1.0 / n, [gF], gp, out_rgb=out_rgb, out_depth=out_dep, loss_out=loss)
+    torch.cuda.synchronize()
+    return gF, gp, out_rgb, out_dep, loss
+
+
+def test_cfg2_train_step_whole_batch_fp32(gpu_lib, cfg2):
+    """The FP32 train step on the whole 2^18-ray batch against the oracle's
+    loss, outputs and gradients.  Rays at a kink of the loss (a decoder ReLU
+    input or the L1 residual within rounding of zero) are part of the batch;
+    the feature rows their hits reach are left out of the per-entry feature
+    comparison (there FP32 and FP64 may take different one-sided
+    derivatives), and their share of every decoder-parameter sum is far below
+    the per-entry bound."""
+    w = cfg2["w"]
+    ob, db, rgb_t, dep_t = cfg2["batch"]
+    n = ob.shape[0]
+    assert n == 1 << 18
+    gF, gp, r, dd, loss = _train_step(gpu_lib, cfg2, "fp32")
+    hits = oracle_trace(cfg2["oc"], ob, db, w.K)
+    er, ed, _, st = oracle_render(cfg2["oc"], cfg2["F"], cfg2["p"], w.widths, ob, db, hits)
+    L, g_rgb, g_dep = oracle_loss(er, ed, rgb_t, dep_t, 0.1)
+    eF, ep = render_backward(st, g_rgb, g_dep)
+    mF, mp, mW = loss_scales(render_backward_hit_magnitude, render_backward_weight_scale, st, g_rgb,
+                             residual_terms(g_rgb, er, rgb_t), g_dep)
+    assert abs(float(loss.item()) - L) <= 1e-5 * abs(L)
+    assert_outputs_close(r.cpu().numpy(), er, 1.0, "cfg2 rgb")
+    assert_outputs_close(dd.cpu().numpy(), ed, max(1.0, np.abs(ed).max()), "cfg2 depth")
+    # a decoder kink changes the backward of its own hit only; the L1 kink
+    # (depth residual at zero) that of every hit of the ray
+    res = ed - dep_t
+    l1_kink = (res != 0) & (np.abs(res) < 1e-4 * np.maximum(1.0, np.abs(dep_t)))
+    hit_k = decoder_kinks(st) | l1_kink[st.ray_i]
+    masked = np.unique(st.corners[hit_k].ravel())
+    reached = np.unique(st.corners.ravel())
+    print(f"cfg2: {st.ray_i.size} hits, {int(hit_k.sum())} at a kink, "
+          f"{masked.size} of {reached.size} feature rows left out")
+    assert masked.size <= 0.2 * reached.size
+    rows = np.ones(eF.shape[0], bool)
+    rows[masked] = False
+    g = gF.cpu().numpy()
+    assert_grad_close(g[rows], eF[rows], "cfg2 grad_features", mag=mF[rows], wmag=mW[rows])
+    assert_grad_close(gp.cpu().numpy(), ep, "cfg2 grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+
+
+def test_cfg2_directional_derivatives_of_gpu_loss(gpu_lib, cfg2):
+    """Central differences along the GPU gradient direction (features, then
+    decoder parameters) of the loss of the GPU's own FP32 render of the whole
+    batch equal the directional derivative |g| that the GPU gradient
+    predicts.  The loss of the rendered colours is summed in FP64 on the host
+    (the per-ray colours differ smoothly between the two evaluations, while
+    the kernel's FP32 sum over 2^18 rays would round the small difference
+    away), with the colour term alone (lambda_depth = 0: the L1 depth term puts
+    a kink at every ray whose depth is near its target, which a finite step
+    would cross; its gradient is checked against the oracle elsewhere)."""
+    import torch
+    w = cfg2["w"]
+    ob, db, rgb_t, dep_t = cfg2["batch"]
+    n = ob.shape[0]
+    opts = gpu_lib.make_opts(w.K, "voxel", "fp32")
+    to, td = _t(ob), _t(db)
+
+    def host_loss(params):
+        rgb, _, _ = gpu_lib.render([cfg2["scene"]], [n], params, w.widths, opts, to, td)
+        torch.cuda.synchronize()
+        r = rgb.cpu().numpy().astype(np.float64) - rgb_t
+        return float(np.sum(r * r)) / (3.0 * n)
+
+    gF, gp, _, _, _ = _train_step(gpu_lib, cfg2, "fp32", lam=0.0)
+    L0 = host_loss(cfg2["params"])
+    F0 = cfg2["scene"].features.clone()
+    p0 = cfg2["params"].clone()
+    for name, g in (("features", gF), ("params", gp)):
+        gn = float(g.double().norm())
+        assert gn > 0
+        v = g / gn
+        eps = 1e-5 * L0 / gn           # moves the loss by about 1e-5 relative
+        vals = []
+        for sgn in (1.0, -1.0):
+            if name == "features":
+                cfg2["scene"].features.copy_(F0 + sgn * eps * v)
+                vals.append(host_loss(p0))
+            else:
+                vals.append(host_loss(p0 + sgn * eps * v))
+        cfg2["scene"].features.copy_(F0)
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        print(f"cfg2 {name}: directional derivative {fd:.6g}, |g| = {gn:.6g}")
+        assert abs(fd - gn) <= 1e-2 * gn, (name, fd, gn)
+
+
+# ------------------------------------------------------------------ 8 scenes
+
+@pytest.fixture(scope="module")
+def multi(gpu_lib):
+    """The full-size ragged workload on the device; features are seeded
+    N(0, 0.4^2) per scene (host FP32, also given to the oracle), the output
+    bias is raised so that compositing matters."""
+    import torch
+    m = get_multi()
+    counts = m.ray_counts()
+    p = m.params()
+    p[-1] = 0.6
+    scs, Fs, dev, os_, ds_ = [], [], [], [], []
+    for i in range(len(m.depths)):
+        sc = m.scene(i)
+        F = np.random.default_rng(300 + i).normal(0.0, 0.4, (sc.n_vertices, m.C)).astype(np.float32)
+        dev.append(gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, F, bf16=True))
+        o, d = m.rays(i, counts[i])
+        scs.append(sc)
+        Fs.append(F)
+        os_.append(o)
+        ds_.append(d)
+        print(f"scene {i}: depth {sc.depth}, {sc.leaf_ijk.shape[0]} leaves, {counts[i]} rays", flush=True)
+    return dict(m=m, counts=counts, p=p, params=torch.from_numpy(p).cuda(), scs=scs, Fs=Fs, dev=dev,
+                o=np.concatenate(os_), d=np.concatenate(ds_))
+
+
+def _multi_sample(mu, i, k, seed):
+    lo = sum(mu["counts"][:i])
+    idx = np.sort(np.random.default_rng(seed + i).choice(mu["counts"][i], k, replace=False))
+    return lo + idx
+
+
+def test_multi_scene_full_size_one_launch(gpu_lib, multi):
+    """One launch per kernel over the 8 full-size scenes: forward (FP32 and
+    BF16) on 2,048 seeded rays per scene against the oracle; the backward over
+    every ray with upstream gradients that vanish except on those rays (kink
+    free), each scene's feature gradient and the shared decoder gradient
+    against the oracle; a HIP graph of the calls replayed three times
+    reproduces the eager results."""
+    import torch
+    mu = multi
+    m, counts = mu["m"], mu["counts"]
+    n = int(sum(counts))
+    to, td = _t(mu["o"]), _t(mu["d"])
+    outs = {}
+    for prec in ("fp32", "bf16"):
+        outs[prec] = gpu_lib.render(mu["dev"], counts, mu["params"], m.widths,
+                                    gpu_lib.make_opts(m.K, "voxel", prec), to, td)
+    torch.cuda.synchronize()
+    outs = {k: [x.cpu().numpy() for x in v] for k, v in outs.items()}
+    g_rgb = np.zeros((n, 3), np.float32)
+    g_dep = np.zeros(n, np.float32)
+    rng = np.random.default_rng(17)
+    ups, states, hit_rays = [], [], 0
+    for i, sc in enumerate(mu["scs"]):
+        oc = Octree(sc.leaf_ijk, sc.depth)
+        F64 = mu["Fs"][i].astype(np.float64)        # converted once per scene (up to 13M rows)
+        idx = _multi_sample(mu, i, 2048, 40)
+        o, d = mu["o"][idx], mu["d"][idx]
+        hits = oracle_trace(oc, o, d, m.K)
+        er, ed, ea, st = oracle_render(oc, F64, mu["p"], m.widths, o, d, hits)
+        r32, d32, a32 = (x[idx] for x in outs["fp32"])
+        assert_outputs_close(r32, er, 1.0, f"scene {i} rgb")
+        assert_outputs_close(d32, ed, max(1.0, np.abs(ed).max()), f"scene {i} depth")
+        assert_outputs_close(a32, ea, 1.0, f"scene {i} acc")
+        br, _, _, _ = oracle_render(oc, F64, mu["p"], m.widths, o, d, hits, bf16=True)
+        assert np.abs(outs["bf16"][0][idx] - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4
+        hit_rays += int(np.count_nonzero(hits[3]))
+        # upstream gradients on the kink-free sampled rays
+        bad = np.zeros(idx.size, bool)
+        bad[np.unique(st.ray_i[decoder_kinks(st)])] = True
+        sel = idx[~bad]
+        g_rgb[sel] = rng.normal(size=(sel.size, 3))
+        g_dep[sel] = rng.normal(size=sel.size) * 0.1
+        _, _, _, st2 = oracle_render(oc, F64, mu["p"], m.widths, mu["o"][sel], mu["d"][sel],
+                                     oracle_trace(oc, mu["o"][sel], mu["d"][sel], m.K))
+        states.append((st2, sel))
+        del F64, oc
+        print(f"scene {i}: {int(np.count_nonzero(hits[3]))} of 2048 sampled rays hit", flush=True)
+    assert hit_rays > 2000
+    gFs = [torch.zeros_like(s.features) for s in mu["dev"]]
+    gp = torch.zeros_like(mu["params"])
+    gpu_lib.render_backward(mu["dev"], counts, mu["params"], m.widths, gpu_lib.make_opts(m.K, "voxel", "fp32"),
+                            to, td, _t(g_rgb), _t(g_dep), None, gFs, gp)
+    torch.cuda.synchronize()
+    ep_total = mp_total = 0.0
+    for i, (st2, sel) in enumerate(states):
+        ups = (g_rgb[sel], g_dep[sel])
+        eF, ep = render_backward(st2, *ups)
+        mF, mp = render_backward_hit_magnitude(st2, *ups)
+        mW = render_backward_weight_scale(st2, *ups)
+        ep_total = ep_total + ep
+        mp_total = mp_total + mp
+        g = gFs[i]
+        # rows the oracle reaches, and every row the GPU wrote
+        gpu_rows = torch.nonzero(g.abs().amax(dim=1) > 0).flatten().cpu().numpy()
+        rows = np.union1d(np.unique(st2.corners.ravel()), gpu_rows).astype(np.int64)
+        got = g[torch.from_numpy(rows).cuda()].cpu().numpy()
+        if rows.size:
+            assert_grad_close(got, eF[rows], f"scene {i} grad_features", mag=mF[rows], wmag=mW[rows])
+    assert_grad_close(gp.cpu().numpy(), ep_total, "8-scene grad_params", rel_nw=1e-4, mag=mp_total, c=C_PARAM)
+
+    # HIP graph of the BF16 forward and train step over all scenes
+    rng = np.random.default_rng(5)
+    t_rgb, t_dep = _t(rng.uniform(0, 1, (n, 3)).astype(np.float32)), _t(rng.uniform(0, 6, n).astype(np.float32))
+    ws = gpu_lib.Workspace()
+    opts = gpu_lib.make_opts(m.K, "voxel", "bf16")
+    out = (torch.empty((n, 3), device="cuda"), torch.empty(n, device="cuda"), torch.empty(n, device="cuda"))
+    loss = torch.zeros(1, device="cuda")
+
+    def work():
+        gpu_lib.render(mu["dev"], counts, mu["params"], m.widths, opts, to, td, *out, workspace=ws)
+        for g in gFs + [gp]:
+            gpu_lib.fill(g, 0.0)
+        gpu_lib.train_step(mu["dev"], counts, mu["params"], m.widths, opts, to, td, t_rgb, t_dep, 0.1,
+                           1.0 / n, gFs, gp, loss_out=loss, workspace=ws)
+
+    work()
+    torch.cuda.synchronize()
+    ref_out = [x.clone() for x in out]
+    ref_g = [g.clone() for g in gFs] + [gp.clone()]
+    ref_loss = float(loss.item())
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            work()
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for x in out:
+            x.fill_(-1.0)
+        loss.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(out, ref_out):
+            assert torch.equal(x, y), rep
+        assert abs(float(loss.item()) - ref_loss) <= 1e-6 * abs(ref_loss)
+        for x, y in zip(gFs + [gp], ref_g):
+            s = float(y.abs().max())
+            assert float((x - y).abs().max()) <= 1e-5 * s + 1e-30, rep
+
+
+# ------------------------------------------------------------- BF16 training
+
+def test_bf16_training_within_0p1_db_of_fp32(gpu_lib):
+    """The depth-7 twelve-ellipsoid scene (16 features per vertex, decoder
+    16-64-64-64-4) trained from the same initial values on the same batches
+    (2^15 rays from the 50 training views per step, 300 steps, Adam) with the
+    BF16 decoder and with the FP32 decoder: held-out PSNR (5 views, 2^16
+    seeded pixels each) of the BF16-trained model is at most 0.1 dB below the
+    FP32-trained one, and training improved both by several dB.  Both runs
+    reduce the feature gradient in a fixed order (SVLF_FLAG_DETERMINISTIC),
+    so each is reproducible: with FP32 atomics the order of additions changes
+    the trajectory by about 0.1 dB from run to run."""
+    import torch
+    from paper_2205_07058_amd.train import Trainer
+    w = get_config(2)
+    sc = w.scene()
+    steps, bsz = 300, 1 << 15
+    batches = [tuple(_t(x) for x in w.train_batch(bsz, step=1000 + it)) for it in range(steps)]
+    held = []
+    for v in w.heldout_views():
+        o, d = w.view_rays(v)
+        idx = np.sort(np.random.default_rng(v).choice(o.shape[0], 1 << 16, replace=False))
+        tgt, _ = w.targets(o[idx], d[idx])
+        held.append((_t(o[idx]), _t(d[idx]), tgt))
+
+    def evaluate(tr):
+        ps = []
+        for o, d, tgt in held:
+            rgb, _, _ = tr.render(o, d)
+            torch.cuda.synchronize()
+            ps.append(psnr(rgb.cpu().numpy(), tgt))
+        return float(np.mean(ps))
+
+    res = {}
+    for prec in ("fp32", "bf16"):
+        scene = gpu_lib.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features(), bf16=True)
+        tr = Trainer(scene, _t(w.params().copy()), w.widths, w.K, precision=prec, lr_features=1e-2,
+                     lr_params=1e-3, deterministic=True)
+        p0 = evaluate(tr)
+        for o, d, rgb, dep in batches:
+            tr.step(o, d, rgb, dep)
+        res[prec] = (p0, evaluate(tr))
+    print(f"held-out PSNR: fp32 {res['fp32'][0]:.3f} -> {res['fp32'][1]:.3f} dB, "
+          f"bf16 {res['bf16'][0]:.3f} -> {res['bf16'][1]:.3f} dB, "
+          f"gap {res['fp32'][1] - res['bf16'][1]:+.3f} dB")
+    assert res["fp32"][1] >= res["fp32"][0] + 3.0
+    assert res["bf16"][1] >= res["fp32"][1] - 0.1
