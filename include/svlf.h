@@ -298,6 +298,31 @@ int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* r
                     float* const* grad_features, float* grad_params,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/* Size of the device scratch array that svlf_train_step_noalloc uses in
+ * place of a workspace (one array per device, held until the process ends). */
+#define SVLF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* svlf_train_step for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same pass, arguments and results as svlf_train_step without the
+ * workspace: the per-ray hit slots and counts and the per-block partial sums
+ * live in a library-owned file-scope device array of
+ * SVLF_NOALLOC_SCRATCH_BYTES (its address is looked up once per device, on
+ * the first call with that device current).  Nothing is allocated or freed.
+ * A call whose workspace (svlf_workspace_bytes_scenes for the same arguments)
+ * exceeds SVLF_NOALLOC_SCRATCH_BYTES fails with SVLF_E_WORKSPACE before
+ * anything is queued (with K = 8 and the 32-64-64-64-4 decoder about 1.7M
+ * rays fit).  The array needs no initialisation; every call on a device
+ * uses the same array, so calls that overlap on one device (other streams,
+ * other host threads) race and must be serialised by the caller. */
+int svlf_train_step_noalloc(const svlf_scene* scenes, int32_t n_scenes,
+                            const int64_t* ray_offsets_host, const svlf_mlp* mlp,
+                            const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                            const float* target_rgb, const float* target_depth,
+                            float lambda_depth, float loss_scale, float* out_rgb, float* out_depth,
+                            float* loss_out, float* const* grad_features, float* grad_params,
+                            void* stream);
+
 /* ---------------------------------------------------------------- light field */
 
 /* The paper's voxel light-field function (section 4.2, Eq. 1-2) in place of

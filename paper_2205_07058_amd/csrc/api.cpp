@@ -188,10 +188,12 @@ DetExtra det_extra(size_t base_total, int64_t n, int K, int C, const svlf_scene&
 }
 
 // Shared body of render / render_backward / train_step.
+// noalloc: no workspace argument; the library's per-device scratch array
+// (svlf_train_step_noalloc) holds the workspace if it is large enough.
 int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_t* offs,
               const svlf_mlp* mlp, const svlf_render_opts* opts, const float* ray_o,
               const float* ray_d, ShadeArgs a, float* const* grad_features, void* ws,
-              size_t ws_bytes, void* stream, const char* who) {
+              size_t ws_bytes, void* stream, const char* who, bool noalloc = false) {
   int rc = check_opts(opts, who);
   if (rc) return rc;
   MlpShape sh;
@@ -211,9 +213,19 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   if (det && n * opts->K >= (int64_t(1) << 31))
     return fail(SVLF_E_RANGE, who_str(who, "too many hit slots for SVLF_FLAG_DETERMINISTIC"));
   const DetExtra dx = det ? det_extra(w.total, n, opts->K, sh.C, scenes[0]) : DetExtra{0, 0, w.total};
-  if (ws == nullptr || ws_bytes < dx.total)
+  if (noalloc) {
+    if (dx.total > SVLF_NOALLOC_SCRATCH_BYTES)
+      return fail(SVLF_E_WORKSPACE,
+                  who_str(who, "the call's workspace (svlf_workspace_bytes_scenes) exceeds "
+                               "SVLF_NOALLOC_SCRATCH_BYTES"));
+    if (n == 0) return SVLF_OK;
+    const hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, who);
+    ws_bytes = SVLF_NOALLOC_SCRATCH_BYTES;
+  } else if (ws == nullptr || ws_bytes < dx.total) {
     return fail(SVLF_E_WORKSPACE, who_str(who, det ? "workspace smaller than svlf_workspace_bytes_scenes()"
                                                    : "workspace missing or smaller than svlf_workspace_bytes()"));
+  }
   if (n == 0) return SVLF_OK;
   char* base = static_cast<char*>(ws);
   a.gxu = det ? reinterpret_cast<float*>(base + dx.gxu) : nullptr;
@@ -691,6 +703,31 @@ int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* r
   a.grad_params = grad_params;
   return run_shade(kTrain, scenes, n_scenes, ray_offsets_host, mlp, opts, ray_o, ray_d, a,
                    grad_features, workspace, ws_bytes, stream, who);
+}
+
+int svlf_train_step_noalloc(const svlf_scene* scenes, int32_t n_scenes,
+                            const int64_t* ray_offsets_host, const svlf_mlp* mlp,
+                            const svlf_render_opts* opts, const float* ray_o, const float* ray_d,
+                            const float* target_rgb, const float* target_depth,
+                            float lambda_depth, float loss_scale, float* out_rgb, float* out_depth,
+                            float* loss_out, float* const* grad_features, float* grad_params,
+                            void* stream) {
+  const char* who = "svlf_train_step_noalloc";
+  if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
+    return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
+  if (!std::isfinite(lambda_depth) || !std::isfinite(loss_scale))
+    return fail(SVLF_E_INVAL, who_str(who, "lambda_depth / loss_scale must be finite"));
+  ShadeArgs a{};
+  a.t_rgb = target_rgb;
+  a.t_depth = target_depth;
+  a.lambda_depth = lambda_depth;
+  a.loss_scale = loss_scale;
+  a.rgb = out_rgb;
+  a.depth = out_depth;
+  a.loss_out = loss_out;
+  a.grad_params = grad_params;
+  return run_shade(kTrain, scenes, n_scenes, ray_offsets_host, mlp, opts, ray_o, ray_d, a,
+                   grad_features, nullptr, 0, stream, who, true);
 }
 
 int svlf_adam_step(float* param, float* grad, float* m, float* v, int64_t n, float lr,

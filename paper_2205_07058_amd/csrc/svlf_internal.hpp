@@ -218,6 +218,10 @@ hipError_t launch_mlp_forward(const float* params, int C, int H, int n_hidden, i
                               int precision, const float* X, int64_t n, float* out,
                               hipStream_t s);
 
+// This device's copy of the library's scratch array of
+// svlf_train_step_noalloc (util.hip; SVLF_NOALLOC_SCRATCH_BYTES).
+hipError_t noalloc_scratch(void** ptr);
+
 // Host octree build (octree_build.cpp).
 struct HostOctree {
   svlf_octree_sizes sizes;

@@ -3,7 +3,16 @@
 // deterministic reduction of per-block MLP-gradient partial sums.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "svlf_internal.hpp"
+
+// The workspace of svlf_train_step_noalloc: a file-scope device array, one
+// copy per device the library runs on, held until the process ends.  Host
+// code never uses this name as an address (on the host it is a stand-in
+// symbol); it takes the device address from hipGetSymbolAddress, once per
+// device, in noalloc_scratch below.
+static __device__ __align__(256) char scratch[SVLF_NOALLOC_SCRATCH_BYTES];
 
 namespace svlf {
 namespace {
@@ -245,6 +254,28 @@ hipError_t launch_reduce_partials(const float* partials, int rows, int64_t n, fl
   hipLaunchKernelGGL(k_reduce, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, partials,
                      rows, n, out, loss_partials, loss_out);
   return hipGetLastError();
+}
+
+// Device address of this device's scratch array, looked up on the first
+// call with that device current and kept per device.
+hipError_t noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* dev_ptr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    dev_ptr[dev] = p;
+  }
+  *ptr = dev_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace svlf

@@ -25,6 +25,7 @@ MAX_DEPTH = 10
 MAX_K = 16
 MAX_SCENES = 16
 MAX_LAYERS = 8
+NOALLOC_SCRATCH_BYTES = 256 << 20      # SVLF_NOALLOC_SCRATCH_BYTES
 
 OK, E_INVAL, E_RANGE, E_WORKSPACE, E_UNSUPPORTED, E_HIP = 0, -1, -2, -3, -4, -5
 TAU_MODES = {"voxel": 0, "direct": 1, "world": 2}
@@ -106,6 +107,11 @@ _SIGS = {
                          ct.c_float, ct.c_float, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                          ct.POINTER(ct.c_void_p), ct.c_void_p, ct.c_void_p, ct.c_size_t,
                          ct.c_void_p], ct.c_int),
+    "svlf_train_step_noalloc": ([ct.POINTER(Scene), ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(Mlp),
+                                 ct.POINTER(RenderOpts), ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                 ct.c_void_p, ct.c_float, ct.c_float, ct.c_void_p, ct.c_void_p,
+                                 ct.c_void_p, ct.POINTER(ct.c_void_p), ct.c_void_p, ct.c_void_p],
+                                ct.c_int),
     "svlf_adam_step": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_float,
                         ct.c_float, ct.c_float, ct.c_float, ct.c_int64, ct.c_void_p, ct.c_int32,
                         ct.c_void_p], ct.c_int),
@@ -485,6 +491,32 @@ def train_step(scenes, ray_counts, params, widths, opts: RenderOpts, ray_o, ray_
                                   _grad_ptrs(grad_features),
                                   _ptr(grad_params, torch.float32, tuple(params.shape), "grad_params"),
                                   _ptr(ws, torch.uint8), nb, _stream()))
+
+
+def train_step_noalloc(scenes, ray_counts, params, widths, opts: RenderOpts, ray_o, ray_d, target_rgb,
+                       target_depth, lambda_depth, loss_scale, grad_features, grad_params,
+                       out_rgb=None, out_depth=None, loss_out=None):
+    """train_step without a workspace (svlf_train_step_noalloc: the library's
+    per-device scratch array; nothing is allocated)."""
+    torch = _torch()
+    scenes = list(scenes) if isinstance(scenes, (list, tuple)) else [scenes]
+    arr, offs, n = _scene_array(scenes, ray_counts)
+    m = make_mlp(params, widths)
+    for g, s in zip(grad_features, scenes):
+        _ptr(g, torch.float32, tuple(s.features.shape), "grad_features")
+    _check("svlf_train_step_noalloc",
+           load().svlf_train_step_noalloc(arr, len(scenes), offs, ct.byref(m), ct.byref(opts),
+                                          _ptr(ray_o, torch.float32, (n, 3), "ray_o"),
+                                          _ptr(ray_d, torch.float32, (n, 3), "ray_d"),
+                                          _ptr(target_rgb, torch.float32, (n, 3), "target_rgb"),
+                                          _ptr(target_depth, torch.float32, (n,), "target_depth"),
+                                          float(lambda_depth), float(loss_scale),
+                                          _ptr(out_rgb, torch.float32, (n, 3), "out_rgb", allow_none=True),
+                                          _ptr(out_depth, torch.float32, (n,), "out_depth", allow_none=True),
+                                          _ptr(loss_out, torch.float32, (1,), "loss_out", allow_none=True),
+                                          _grad_ptrs(grad_features),
+                                          _ptr(grad_params, torch.float32, tuple(params.shape), "grad_params"),
+                                          _stream()))
 
 
 # ------------------------------------------------------------------ utilities

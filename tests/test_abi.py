@@ -298,3 +298,31 @@ def test_deterministic_workspace_query(lib):
     assert base == lib.svlf_workspace_bytes(ct.byref(m), ct.byref(plain), 100)
     det = lib.svlf_workspace_bytes_scenes(ct.byref(m), ct.byref(opts), sc, 1, 100)
     assert det >= base + 100 * 8 * (8 + 4) * 4 + 3000 * 32
+
+
+def test_noalloc_train_step_rejects_oversized_calls_before_device_work(lib):
+    """svlf_train_step_noalloc: a call whose workspace exceeds the library's
+    scratch array fails with SVLF_E_WORKSPACE during host validation (here on
+    a machine without a GPU: nothing reaches the device)."""
+    m = _mlp((32, 64, 64, 64, 4))
+    opts = svlf.make_opts(8)
+    sc = (svlf.Scene * 1)()
+    sc[0].octree.depth = 4        # empty scene: only the size check can fail
+    n = 4 << 20
+    offs = (ct.c_int64 * 2)(0, n)
+    need = lib.svlf_workspace_bytes(ct.byref(m), ct.byref(opts), n)
+    assert need > svlf.NOALLOC_SCRATCH_BYTES
+    grads = (ct.c_void_p * 1)(0x100)
+    p = ct.c_void_p(0x100)
+    rc = lib.svlf_train_step_noalloc(sc, 1, offs, ct.byref(m), ct.byref(opts), p, p, p, p, 0.1, 1.0,
+                                     None, None, None, grads, p, None)
+    assert rc == svlf.E_WORKSPACE and "SVLF_NOALLOC_SCRATCH_BYTES" in svlf.last_error()
+    # the size limit is the documented one: the largest ray count that fits
+    fit = 1
+    while lib.svlf_workspace_bytes(ct.byref(m), ct.byref(opts), 2 * fit) <= svlf.NOALLOC_SCRATCH_BYTES:
+        fit *= 2
+    assert fit >= 1 << 20
+    # other validation still comes first
+    rc = lib.svlf_train_step_noalloc(sc, 1, offs, ct.byref(m), ct.byref(opts), p, p, None, p, 0.1, 1.0,
+                                     None, None, None, grads, p, None)
+    assert rc == svlf.E_INVAL
