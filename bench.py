@@ -307,13 +307,27 @@ def main():
         cpu = cpu_baseline(args, ob, db, rgb_t, dep_t)
 
     # roofline of the dominant kernel (the fused shading kernel of the BF16
-    # train step): algorithmic bytes per launch over its event-timed duration
+    # train step): algorithmic bytes per launch over its event-timed duration.
+    # The algorithmic count of a training pass: per ray its origin and
+    # direction, outputs, targets and output gradients (24 + 16 + 16 + 16 B);
+    # per hit the gather of the corner ids and 8 BF16 feature rows in the
+    # forward and again in the backward, the FP32 gradient read-modify-write
+    # of the 8 rows, and the hit list written by the forward and read by the
+    # backward (24 B per slot, K slots per ray, over the hits per ray); plus
+    # the per-block decoder-gradient partials.  The fused kernel gathers once
+    # and keeps the hit list on chip; its own count is reported beside it.
     C = w.C
+    K = w.K
     n_params = p.size
     grid = 256                                    # one block per CU for the BF16 train kernel
-    bytes_ray = 24 + 4 + 16                      # o, d, hit count, targets
-    bytes_hit = 16 + 32 + 8 * C * 2 + 8 * C * 4 * 2   # hit record, corners, BF16 rows, FP32 grad RMW
+    hbar = hits_b / n_b
+    b_gather = 32 + 8 * C * 2
+    bytes_ray = 24 + 16 + 16 + 16
+    bytes_hit = 2 * b_gather + 8 * C * 4 * 2 + 24 * K / hbar
     bytes_launch = n_b * bytes_ray + hits_b * bytes_hit + grid * n_params * 4
+    fused_ray = 24 + 4 + 16                       # o, d, hit count, targets
+    fused_hit = 16 + b_gather + 8 * C * 4 * 2     # hit record, one gather, gradient RMW
+    fused_launch = n_b * fused_ray + hits_b * fused_hit + grid * n_params * 4
     roof = None
     if stages:
         sh_ms = stages["shade_reduce_ms"]
@@ -328,7 +342,9 @@ def main():
                 "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                 "kernel": "k_shade<bf16,32,64,3,train> + k_reduce",
                 "bytes_per_launch": int(bytes_launch),
-                "bytes_per_hit": bytes_hit, "bytes_per_ray": bytes_ray, "hits_per_ray": round(hits_b / n_b, 4)}
+                "bytes_per_hit": round(bytes_hit, 1), "bytes_per_ray": bytes_ray, "hits_per_ray": round(hbar, 4),
+                "fused_kernel_bytes_per_launch": int(fused_launch), "fused_kernel_bytes_per_hit": fused_hit,
+                "fused_kernel_frac": round(fused_launch / (sh_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     ms = res.get("train_bf16_ms")
     value = n_b / (ms * 1e-3) if ms else None
