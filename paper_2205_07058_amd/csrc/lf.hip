@@ -718,12 +718,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
                 for (int rr = g; rr < kLfH; rr += 2) AT[rr * CF::TS + col] = to_el<BF>(0.0f);
             }
           }
-          if constexpr (l == 0) {
-            for (int e = tid; e < CF::WIN * CF::XT_ROWS; e += kThreads) {
-              const int hh = e % CF::WIN, c = e / CF::WIN;
-              AT[c * CF::TS + hh] = c < M::IN0P ? dX<CF>()[hh * CF::XS + c] : to_el<BF>(0.0f);
-            }
-          }
+          if constexpr (l == 0)
+            transpose_tile<BF, CF::WIN, CF::XS, CF::TS, M::IN0P, CF::XT_ROWS, kThreads>(dX<CF>(), AT, tid);
           __syncthreads();
           dw_window<BF, M, l, CF::WIN, CF::TS>(GZ, AT, part, wave, lane);
           bias_part<BF, M::out_p(l), M::out_r(l), CF::WIN, CF::TS>(GZ, tid, dbp[l]);
@@ -1194,12 +1190,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
             }
           }
           El* XTs = CF::ACT_REG ? cACT<CF>() : XT;      // X^T (layer 0)
-          if constexpr (l == 0) {
-            for (int e = tid; e < CF::WIN * CF::XT_ROWS; e += kThreads) {
-              const int hh = e % CF::WIN, c = e / CF::WIN;
-              XTs[c * CF::TS + hh] = c < M::IN0P ? cX<CF>()[hh * CF::XS + c] : to_el<BF>(0.0f);
-            }
-          }
+          if constexpr (l == 0)
+            transpose_tile<BF, CF::WIN, CF::XS, CF::TS, M::IN0P, CF::XT_ROWS, kThreads>(cX<CF>(), XTs, tid);
           __syncthreads();
           // layer l's input: X^T (l = 0), layer 0 from LDS, or the staged register layer
           const El* AT = (l == 0) ? XTs

@@ -143,6 +143,47 @@ __device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total) {
   return pre + x - v;
 }
 
+// Transposes the first ROWS columns of an LDS tile X [WIN][XS] (one row per
+// hit; columns >= REAL read as zero) into AT [ROWS][TS] (one row per column,
+// AT[c * TS + hit]).  Each thread moves a block of 2 hits x 8 columns
+// (BF16) or 1 hit x 4 columns (FP32): 16-byte reads of X rows, and for BF16
+// 32-bit writes that pack the two hits' values, so that consecutive lanes
+// touch consecutive LDS words (a one-element-per-lane transpose reads X at
+// the row stride, a 4-way bank conflict for these strides).
+template <bool BF, int WIN, int XS, int TS, int REAL, int ROWS, int NT, class El>
+__device__ __forceinline__ void transpose_tile(const El* X, El* AT, int tid) {
+  if constexpr (BF) {
+    static_assert(XS % 8 == 0 && TS % 2 == 0 && WIN % 2 == 0 && ROWS % 8 == 0, "BF16 transpose blocks");
+    constexpr int HP = WIN / 2, UNITS = HP * (ROWS / 8);
+    for (int u = tid; u < UNITS; u += NT) {
+      const int hp = u % HP, ch = u / HP, c0 = 8 * ch;
+      uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
+      if (c0 < REAL) {
+        r0 = *reinterpret_cast<const uint4*>(X + (2 * hp) * XS + c0);
+        r1 = *reinterpret_cast<const uint4*>(X + (2 * hp + 1) * XS + c0);
+      }
+      const uint32_t a[4] = {r0.x, r0.y, r0.z, r0.w}, b[4] = {r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t* lo = reinterpret_cast<uint32_t*>(AT + (c0 + 2 * k) * TS + 2 * hp);
+        uint32_t* hi = reinterpret_cast<uint32_t*>(AT + (c0 + 2 * k + 1) * TS + 2 * hp);
+        *lo = (a[k] & 0xFFFFu) | (b[k] << 16);
+        *hi = (a[k] >> 16) | (b[k] & 0xFFFF0000u);
+      }
+    }
+  } else {
+    static_assert(XS % 4 == 0 && ROWS % 4 == 0, "FP32 transpose blocks");
+    constexpr int UNITS = WIN * (ROWS / 4);
+    for (int u = tid; u < UNITS; u += NT) {
+      const int hh = u % WIN, c0 = 4 * (u / WIN);
+      f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (c0 < REAL) v = *reinterpret_cast<const f32x4*>(X + hh * XS + c0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) AT[(c0 + k) * TS + hh] = v[k];
+    }
+  }
+}
+
 template <int NW>
 __device__ __forceinline__ float block_sum(float v, float* scr) {
 #pragma unroll

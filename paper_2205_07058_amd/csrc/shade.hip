@@ -750,12 +750,8 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
                 for (int rr = g; rr < CF::H; rr += 2) sm.AT()[rr * CF::TS + col] = to_elem<CF>(0.0f);
             }
           }
-          if constexpr (l == 0) {
-            for (int e = tid; e < CF::WIN * CF::CI; e += kThreads) {
-              const int hh = e % CF::WIN, c = e / CF::WIN;
-              sm.AT()[c * CF::TS + hh] = sm.X()[hh * CF::XS + c];
-            }
-          }
+          if constexpr (l == 0)
+            transpose_tile<CF::BF, CF::WIN, CF::XS, CF::TS, CF::CI, CF::CI, kThreads>(sm.X(), sm.AT(), tid);
           __syncthreads();
           // owned dW tiles of layer l: K = the window's hits
           {
