@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -187,6 +188,41 @@ DetExtra det_extra(size_t base_total, int64_t n, int K, int C, const svlf_scene&
   return d;
 }
 
+// The library's side stream on the current device (default priority,
+// non-blocking) with the two events of a fork / join, created on first use
+// and kept until the process ends.  The returned lock serialises the
+// fork-join sequences of concurrent calls.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+hipError_t side_stream(SideStream** out, std::unique_lock<std::mutex>* lock) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static SideStream per[kMaxDevices];
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::unique_lock<std::mutex> l(mu);
+  SideStream& ss = per[dev];
+  if (ss.stream == nullptr) {
+    hipStream_t st = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    ss.stream = st;
+    ss.fork = f;
+    ss.join = j;
+  }
+  *out = &ss;
+  *lock = std::move(l);
+  return hipSuccess;
+}
+
 // Shared body of render / render_backward / train_step.
 // noalloc: no workspace argument; the library's per-device scratch array
 // (svlf_train_step_noalloc) holds the workspace if it is large enough.
@@ -252,19 +288,46 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
     if (e != hipSuccess) return hip_fail(e, who);
   }
   if (opts->flags & SVLF_FLAG_TRACE_ONLY) return SVLF_OK;
-  int grid = 0;
-  e = launch_shade(a, mode, s, &grid);
-  if (e == hipErrorNotSupported)
-    return fail(SVLF_E_UNSUPPORTED, who_str(who, "no kernel for this MLP shape / precision"));
-  if (e != hipSuccess) return hip_fail(e, who);
-  if (mode != kForward) {
-    e = launch_reduce_partials(a.ws_partials, grid, sh.n_params, a.grad_params, a.ws_loss,
-                               mode == kTrain ? a.loss_out : nullptr, s);
+  const int64_t n_leaves = scenes[0].octree.n_leaves, n_vertices = scenes[0].octree.n_vertices;
+  void* det_scratch = base + dx.scratch;
+  // Deterministic mode: the ordering of the hits needs only the hit lists,
+  // so it runs on the library's side stream while the shading kernel runs
+  // (fork after the traversal, join before the per-vertex sum); calls
+  // without a workspace argument keep everything on the caller's stream.
+  std::unique_lock<std::mutex> fork_lock;
+  SideStream* side = nullptr;
+  if (det && !noalloc) {
+    e = side_stream(&side, &fork_lock);
+    if (e != hipSuccess) return hip_fail(e, who);
+    e = hipEventRecord(side->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+    if (e == hipSuccess)
+      e = launch_detgrad_order(a.tab.s[0], a.hits, a.cnt, n, opts->K, sh.C, det_scratch, n_leaves,
+                               n_vertices, side->stream);
+    if (e == hipSuccess) e = hipEventRecord(side->join, side->stream);
     if (e != hipSuccess) return hip_fail(e, who);
   }
+  int grid = 0;
+  e = launch_shade(a, mode, s, &grid);
+  if (e == hipSuccess && mode != kForward)
+    e = launch_reduce_partials(a.ws_partials, grid, sh.n_params, a.grad_params, a.ws_loss,
+                               mode == kTrain ? a.loss_out : nullptr, s);
+  if (e != hipSuccess) {
+    if (side) hipStreamWaitEvent(s, side->join, 0);     // join the fork on every path
+    if (e == hipErrorNotSupported)
+      return fail(SVLF_E_UNSUPPORTED, who_str(who, "no kernel for this MLP shape / precision"));
+    return hip_fail(e, who);
+  }
   if (det) {
-    e = launch_detgrad(a.tab.s[0], a.hits, a.cnt, n, opts->K, sh.C, a.gxu, base + dx.scratch,
-                       scenes[0].octree.n_leaves, scenes[0].octree.n_vertices, s);
+    if (side) {
+      e = hipStreamWaitEvent(s, side->join, 0);
+    } else {
+      e = launch_detgrad_order(a.tab.s[0], a.hits, a.cnt, n, opts->K, sh.C, det_scratch, n_leaves,
+                               n_vertices, s);
+    }
+    if (e == hipSuccess)
+      e = launch_detgrad_sum(a.tab.s[0], n, opts->K, sh.C, a.gxu, det_scratch, n_leaves,
+                             n_vertices, s);
     if (e != hipSuccess) return hip_fail(e, who);
   }
   return SVLF_OK;

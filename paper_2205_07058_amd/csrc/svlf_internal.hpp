@@ -115,13 +115,17 @@ struct ShadeArgs {
   float* gxu;             // deterministic mode: [n][K][C + 4] (u, dL/dx) per hit, else null
 };
 
-// Deterministic feature-gradient reduction (detgrad.hip): bucket the hit
-// slots by leaf, order each bucket by slot, and sum per vertex over its
-// (up to 8) adjacent leaves in a fixed order.
+// Deterministic feature-gradient reduction (detgrad.hip): the order step
+// (needs only the hit lists) sorts the hits by leaf, stably in slot order,
+// and builds the vertex-to-leaf table; the sum step (after the backward has
+// written the per-hit records gxu) sums per vertex over its (up to 8)
+// adjacent leaves in a fixed order.
 size_t detgrad_bytes(int64_t n_rays, int K, int C, int64_t n_leaves, int64_t n_vertices);
-hipError_t launch_detgrad(const DevScene& sc, const HitRec* hits, const int32_t* cnt,
-                          int64_t n_rays, int K, int C, const float* gxu, void* scratch,
-                          int64_t n_leaves, int64_t n_vertices, hipStream_t s);
+hipError_t launch_detgrad_order(const DevScene& sc, const HitRec* hits, const int32_t* cnt,
+                                int64_t n_rays, int K, int C, void* scratch, int64_t n_leaves,
+                                int64_t n_vertices, hipStream_t s);
+hipError_t launch_detgrad_sum(const DevScene& sc, int64_t n_rays, int K, int C, const float* gxu,
+                              void* scratch, int64_t n_leaves, int64_t n_vertices, hipStream_t s);
 
 enum ShadeMode { kForward = 0, kBackward = 1, kTrain = 2 };
 

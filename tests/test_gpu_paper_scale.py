@@ -176,6 +176,55 @@ def test_deterministic_train_step_paper_scale(gpu_lib, paper):
     assert scale > 0 and np.abs(a - c).max() <= 1e-5 * scale
 
 
+def test_deterministic_train_step_from_hip_graph(gpu_lib, paper):
+    """The deterministic train step orders the hits on a side stream while
+    the shading kernel runs (a fork / join): captured in a HIP graph and
+    replayed three times, with eager work between the replays, it gives
+    the eager call's feature and decoder gradients bit for bit."""
+    import torch
+    w = paper["w"]
+    ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=1)
+    n = ob.shape[0]
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    args = [T(ob), T(db), T(rgb_t), T(dep_t)]
+    ws = gpu_lib.Workspace()
+    opts = gpu_lib.make_opts(w.K, "voxel", "bf16", gpu_lib.FLAG_DETERMINISTIC)
+    gF = torch.zeros_like(paper["scene"].features)
+    gp = torch.zeros_like(paper["params"])
+    loss = torch.zeros(1, device="cuda")
+
+    def work():
+        gpu_lib.fill(gF, 0.0)
+        gpu_lib.fill(gp, 0.0)
+        gpu_lib.train_step([paper["scene"]], [n], paper["params"], w.widths, opts, *args, 0.1,
+                           1.0 / n, [gF], gp, loss_out=loss, workspace=ws)
+
+    work()
+    torch.cuda.synchronize()
+    ref = (gF.clone(), gp.clone(), loss.clone())
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            work()
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        gF.fill_(-1.0)
+        gp.fill_(-1.0)
+        loss.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gF, ref[0]), rep
+        assert torch.equal(gp, ref[1]), rep
+        assert torch.equal(loss, ref[2]), rep
+        work()                                    # eager call between replays
+        torch.cuda.synchronize()
+        assert torch.equal(gF, ref[0]), rep
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_train_step_full_batch_equals_chunked_calls(gpu_lib, paper, precision):
     """The shading kernels interleave the rays of groups of 256 full work

@@ -7,7 +7,7 @@ import pytest
 from oracle.render import (bf16_round, loss as oracle_loss, mlp_forward as oracle_mlp, render_backward,
                            render_backward_hit_magnitude,
                            render_backward_weight_scale)
-from synth.configs import get_config, tiny_workload, xavier_params
+from synth.configs import get_config, scene_from_leaves, tiny_workload, xavier_params
 from tests.gpu_cases import (C_PARAM, C_W_LF, Case, assert_grad_close, assert_outputs_close, psnr,
                              loss_scales, residual_terms)
 from tests.helpers import random_rays
@@ -305,6 +305,52 @@ def test_deterministic_feature_gradient(gpu_lib):
         assert_grad_close(gF1, eF, f"{name} deterministic grad_features", mag=mF, wmag=mW)
         assert_grad_close(gF1, gFa, f"{name} deterministic vs atomic", mag=mF, wmag=mW)
         np.testing.assert_array_equal(gp1, gpa)
+
+
+def test_deterministic_feature_gradient_hit_dense_coarse_scene(gpu_lib):
+    """SVLF_FLAG_DETERMINISTIC where leaf buckets are large: every cell of a
+    depth-2 grid is a leaf (64 leaves) and 2^16 rays put thousands of hits
+    in each bucket.  Bit-identical repeats, the oracle on kink-free rays,
+    and the atomic path, all within the per-entry bound."""
+    import torch
+    cells = [(i, j, k) for i in range(4) for j in range(4) for k in range(4)]
+    w = scene_from_leaves(11, 2, 8, (8, 32, 32, 4), 8, cells)
+    case = Case.from_workload(gpu_lib, w, feat_scale=2.0, sigma_bias=0.05)
+    rng = np.random.default_rng(43)
+    o, d = random_rays(rng, 1 << 16, inside_frac=0.3)
+    keep = case.smooth_rays(o, d)
+    o, d = o[keep], d[keep]
+    n = o.shape[0]
+    assert n > 30000
+    _, _, _, st = case.oracle(o, d)
+    # a leaf's lowest corner identifies it
+    _, per_leaf = np.unique(st.corners[:, 0], return_counts=True)
+    print(f"hit-dense scene: {n} rays, {per_leaf.sum()} hits, bucket sizes {per_leaf.min()}..{per_leaf.max()}")
+    assert per_leaf.size == 64 and per_leaf.min() > 1000
+    g_rgb = rng.normal(size=(n, 3)).astype(np.float32)
+    g_dep = rng.normal(size=n).astype(np.float32)
+    to, td = case.rays(o, d)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+
+    def run(flags):
+        gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+        gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+        opts = gpu_lib.make_opts(case.K, case.tau_mode, "fp32", flags)
+        gpu_lib.render_backward([case.scene], [n], case.params, case.widths, opts, to, td,
+                                t(g_rgb), t(g_dep), None, [gF], gp)
+        torch.cuda.synchronize()
+        return gF.cpu().numpy(), gp.cpu().numpy()
+
+    gF1, gp1 = run(gpu_lib.FLAG_DETERMINISTIC)
+    gF2, _ = run(gpu_lib.FLAG_DETERMINISTIC)
+    assert np.array_equal(gF1.view(np.int32), gF2.view(np.int32))
+    gFa, gpa = run(0)
+    eF, _ = render_backward(st, g_rgb, g_dep)
+    mF, _ = render_backward_hit_magnitude(st, g_rgb, g_dep)
+    mW = render_backward_weight_scale(st, g_rgb, g_dep)
+    assert_grad_close(gF1, eF, "hit-dense deterministic grad_features", mag=mF, wmag=mW)
+    assert_grad_close(gF1, gFa, "hit-dense deterministic vs atomic", mag=mF, wmag=mW)
+    np.testing.assert_array_equal(gp1, gpa)
 
 
 def test_max_K_solid_scene(gpu_lib):
