@@ -495,6 +495,8 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     constexpr bool PIPE = CF::BWD;   // forward kernels: slower so (at their register cap)
     static_assert(!PIPE || NPASS == GRP, "one gather group per window");
     const int q = tid % TPH;
+    // raw feature rows of a hit's 8 corners: 16 bytes per corner and thread
+    using Raw = typename std::conditional<CF::BF, uint4, float4>::type;
     struct Stage {
       int hh[GRP];
       bool val[GRP];
@@ -502,6 +504,9 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
       float ro[GRP][3], rd[GRP][3];
       int4 c0[GRP], c1[GRP];
     };
+    // one window's raw rows: filled for the next window after this one's
+    // compositing, consumed when the next window starts
+    Raw raw[GRP][8];
     auto stage_a = [&](Stage& st, int pb, int hb, int twin) {
 #pragma unroll
       for (int k = 0; k < GRP; ++k) {
@@ -526,7 +531,24 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         }
       }
     };
-    auto stage_c = [&](Stage& st) {
+    // (C, issue) the 8 corner rows of each hit into registers
+    auto stage_c_issue = [&](const Stage& st) {
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+        if (!st.val[k]) continue;
+        const int vid[8] = {st.c0[k].x, st.c0[k].y, st.c0[k].z, st.c0[k].w,
+                            st.c1[k].x, st.c1[k].y, st.c1[k].z, st.c1[k].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if constexpr (CF::BF)
+            raw[k][j] = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * CF::C + 8 * q);
+          else
+            raw[k][j] = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * CF::C + 4 * q);
+        }
+      }
+    };
+    // (C, consume) trilinear weights, the hit's LDS record and its row of X
+    auto stage_c_consume = [&](Stage& st) {
       float v[GRP][VPT];
 #pragma unroll
       for (int k = 0; k < GRP; ++k) {
@@ -555,22 +577,19 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
           rc.v1 = st.c1[k];
           sm.rec(rb)[st.hh[k]] = rc;
         }
-        const int vid[8] = {st.c0[k].x, st.c0[k].y, st.c0[k].z, st.c0[k].w,
-                            st.c1[k].x, st.c1[k].y, st.c1[k].z, st.c1[k].w};
         const float wx[2] = {1.0f - ux, ux}, wy[2] = {1.0f - uy, uy}, wz[2] = {1.0f - uz, uz};
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const float wj = wx[j & 1] * wy[(j >> 1) & 1] * wz[j >> 2];
           if constexpr (CF::BF) {
-            const uint4 raw = *reinterpret_cast<const uint4*>(sc.feat16 + static_cast<int64_t>(vid[j]) * CF::C + 8 * q);
-            const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+            const uint32_t w4[4] = {raw[k][j].x, raw[k][j].y, raw[k][j].z, raw[k][j].w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               v[k][2 * i] += wj * bf16_f32(static_cast<uint16_t>(w4[i] & 0xFFFFu));
               v[k][2 * i + 1] += wj * bf16_f32(static_cast<uint16_t>(w4[i] >> 16));
             }
           } else {
-            const float4 f = *reinterpret_cast<const float4*>(sc.feat32 + static_cast<int64_t>(vid[j]) * CF::C + 4 * q);
+            const float4 f = raw[k][j];
             v[k][0] += wj * f.x;
             v[k][1] += wj * f.y;
             v[k][2] += wj * f.z;
@@ -594,6 +613,10 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
           }
         }
       }
+    };
+    auto stage_c = [&](Stage& st) {
+      stage_c_issue(st);
+      stage_c_consume(st);
     };
 
     Stage cur, nxt;
@@ -619,9 +642,10 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
         if (!have_next) {
           stage_a(cur, 0, hb, tw);
           stage_b(cur);
+          stage_c_issue(cur);
         }
         if (pre) stage_a(nxt, 0, hb ^ 1, s1n - s1);
-        stage_c(cur);
+        stage_c_consume(cur);
       } else {
 #pragma unroll 1
         for (int pb = 0; pb < NPASS; pb += GRP) {
@@ -721,6 +745,9 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
       }
 
       if constexpr (CF::BWD) {
+        // the next window's corner rows: loaded while this window's
+        // backward runs from LDS and registers
+        if (pre) stage_c_issue(nxt);
         __syncthreads();
         // output-layer gradient tile (rows 0..3 = dL/do, zero elsewhere)
         f32x16 gz[CF::MTH];
