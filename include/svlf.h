@@ -179,11 +179,15 @@ typedef struct {
 #define SVLF_FLAG_VIEWDIR 4
 /* SVLF_FLAG_DETERMINISTIC (svlf_render_backward, svlf_train_step; one scene):
  * the feature gradient is reduced in a fixed order instead of with FP32
- * atomics, so repeated calls on the same inputs give bit-identical
- * gradients.  The backward keeps (u, dL/dx) per hit; the hits are bucketed
- * by leaf (counting sort, each bucket in ascending hit-slot order) and every
- * vertex sums over its up to 8 adjacent leaves in a fixed order.  The
- * workspace must then come from svlf_workspace_bytes_scenes. */
+ * atomics, and every work item stays on a fixed block, so repeated calls on
+ * the same inputs give bit-identical feature and decoder gradients and
+ * loss.  The backward keeps (u, dL/dx) per hit; the hits are sorted by leaf
+ * (stable, each leaf's hits in ascending hit-slot order) and every vertex
+ * sums over its up to 8 adjacent leaves in a fixed order.  The workspace
+ * must then come from svlf_workspace_bytes_scenes.  Without the flag the
+ * feature gradient takes FP32 atomics and the last work items go to
+ * whichever block is free, so both gradients and the loss may differ in
+ * their last bits between calls. */
 #define SVLF_FLAG_DETERMINISTIC 8
 
 /* ---------------------------------------------------------------- octree */

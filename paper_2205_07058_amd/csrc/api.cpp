@@ -155,8 +155,9 @@ int make_table(const svlf_scene* scenes, int n_scenes, const int64_t* offs, bool
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace: [hit slots n*K][counts n][per-block dW partials][per-block loss]
+// [work-item counter]
 struct WsLayout {
-  size_t hits, cnt, partials, loss, total;
+  size_t hits, cnt, partials, loss, counter, total;
 };
 
 WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
@@ -170,6 +171,8 @@ WsLayout ws_layout(int64_t n_rays, int K, int64_t n_params) {
   off = align256(off + static_cast<size_t>(shade_grid_limit()) * n_params * sizeof(float));
   w.loss = off;
   off = align256(off + static_cast<size_t>(shade_grid_limit()) * sizeof(float));
+  w.counter = off;
+  off = align256(off + sizeof(int32_t));
   w.total = off;
   return w;
 }
@@ -271,6 +274,8 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
   a.cnt = reinterpret_cast<int32_t*>(base + w.cnt);
   a.ws_partials = reinterpret_cast<float*>(base + w.partials);
   a.ws_loss = reinterpret_cast<float*>(base + w.loss);
+  // deterministic mode keeps every item on a fixed block (fixed-order decoder-gradient partials)
+  a.item_counter = det ? nullptr : reinterpret_cast<int32_t*>(base + w.counter);
   a.K = opts->K;
   a.tau_mode = opts->tau_mode;
   a.precision = opts->precision;
@@ -308,7 +313,9 @@ int run_shade(int mode, const svlf_scene* scenes, int32_t n_scenes, const int64_
     if (e != hipSuccess) return hip_fail(e, who);
   }
   int grid = 0;
-  e = launch_shade(a, mode, s, &grid);
+  if (a.item_counter != nullptr)
+    e = launch_fill(reinterpret_cast<float*>(a.item_counter), 0.0f, 1, s);   // 0.0f has zero bits
+  if (e == hipSuccess) e = launch_shade(a, mode, s, &grid);
   if (e == hipSuccess && mode != kForward)
     e = launch_reduce_partials(a.ws_partials, grid, sh.n_params, a.grad_params, a.ws_loss,
                                mode == kTrain ? a.loss_out : nullptr, s);

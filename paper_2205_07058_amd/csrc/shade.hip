@@ -404,6 +404,19 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
   const int G = gridDim.x, b = blockIdx.x;
   const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   const int NB = a.tab.n_blocks;
+  // The last two rounds of items are handed out in order by a counter to
+  // whichever block is free, so that blocks whose items held fewer hits
+  // take more of them and the launch does not wait on the slowest block.
+  const int n_tail = a.item_counter != nullptr ? (NB < 2 * G ? NB : 2 * G) : 0;
+  const int n_static = NB - n_tail;
+  auto tail_item = [&]() -> int {
+    if (n_tail == 0) return NB;                 // no counter: every item is dealt statically
+    if (tid == 0) sm.scr()[9] = n_static + atomicAdd(a.item_counter, 1);
+    __syncthreads();
+    const int it = sm.scr()[9];
+    __syncthreads();
+    return it;
+  };
 
   // Backward: a window's feature-gradient atomics are issued after the next
   // window's gather, so that the gather's loads do not queue behind them
@@ -439,7 +452,8 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
 
   __syncthreads();
 
-  for (int item = lb; item < NB; item += G) {
+  for (int item = lb < n_static ? lb : tail_item(); item < NB;
+       item = item + G < n_static ? item + G : tail_item()) {
     int si = 0;
     while (si + 1 < a.tab.n && item >= a.tab.s[si + 1].block_begin) ++si;
     const DevScene& sc = a.tab.s[si];

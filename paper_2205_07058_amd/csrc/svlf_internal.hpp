@@ -113,6 +113,7 @@ struct ShadeArgs {
   float* ws_loss;         // [grid] per-block loss partial sums
   int64_t n_params;
   float* gxu;             // deterministic mode: [n][K][C + 4] (u, dL/dx) per hit, else null
+  int32_t* item_counter;  // zeroed before the launch: hands out the last work items (nullable)
 };
 
 // Deterministic feature-gradient reduction (detgrad.hip): the order step

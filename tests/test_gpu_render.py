@@ -272,7 +272,9 @@ def test_multi_scene_render_and_backward(gpu_lib):
 def test_deterministic_feature_gradient(gpu_lib):
     """SVLF_FLAG_DETERMINISTIC: bit-identical feature gradients over repeated
     calls, equal to the atomic path within the FP32 tolerance, and to the
-    oracle on kink-free rays; decoder gradients unchanged."""
+    oracle on kink-free rays; decoder gradients bit-identical over repeated
+    calls too, and equal to the atomic path's and the oracle's within the
+    decoder-gradient bound."""
     import torch
     for name, case in list(_scene_cases(gpu_lib))[:3]:
         rng = np.random.default_rng(41)
@@ -295,16 +297,20 @@ def test_deterministic_feature_gradient(gpu_lib):
             return gF.cpu().numpy(), gp.cpu().numpy()
 
         gF1, gp1 = run(gpu_lib.FLAG_DETERMINISTIC)
-        gF2, _ = run(gpu_lib.FLAG_DETERMINISTIC)
+        gF2, gp2 = run(gpu_lib.FLAG_DETERMINISTIC)
         assert np.array_equal(gF1.view(np.int32), gF2.view(np.int32)), name
+        assert np.array_equal(gp1.view(np.int32), gp2.view(np.int32)), name
         gFa, gpa = run(0)
         _, _, _, st = case.oracle(o, d)
         eF, ep = render_backward(st, g_rgb, g_dep)
-        mF, _ = render_backward_hit_magnitude(st, g_rgb, g_dep)
+        mF, mp = render_backward_hit_magnitude(st, g_rgb, g_dep)
         mW = render_backward_weight_scale(st, g_rgb, g_dep)
         assert_grad_close(gF1, eF, f"{name} deterministic grad_features", mag=mF, wmag=mW)
         assert_grad_close(gF1, gFa, f"{name} deterministic vs atomic", mag=mF, wmag=mW)
-        np.testing.assert_array_equal(gp1, gpa)
+        # without the flag the last work items go to whichever block is free,
+        # so the per-block decoder-gradient partials are grouped differently
+        assert_grad_close(gp1, ep, f"{name} deterministic grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+        assert_grad_close(gpa, gp1, f"{name} atomic vs deterministic grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
 
 
 def test_deterministic_feature_gradient_hit_dense_coarse_scene(gpu_lib):
@@ -342,15 +348,17 @@ def test_deterministic_feature_gradient_hit_dense_coarse_scene(gpu_lib):
         return gF.cpu().numpy(), gp.cpu().numpy()
 
     gF1, gp1 = run(gpu_lib.FLAG_DETERMINISTIC)
-    gF2, _ = run(gpu_lib.FLAG_DETERMINISTIC)
+    gF2, gp2 = run(gpu_lib.FLAG_DETERMINISTIC)
     assert np.array_equal(gF1.view(np.int32), gF2.view(np.int32))
+    assert np.array_equal(gp1.view(np.int32), gp2.view(np.int32))
     gFa, gpa = run(0)
-    eF, _ = render_backward(st, g_rgb, g_dep)
-    mF, _ = render_backward_hit_magnitude(st, g_rgb, g_dep)
+    eF, ep = render_backward(st, g_rgb, g_dep)
+    mF, mp = render_backward_hit_magnitude(st, g_rgb, g_dep)
     mW = render_backward_weight_scale(st, g_rgb, g_dep)
     assert_grad_close(gF1, eF, "hit-dense deterministic grad_features", mag=mF, wmag=mW)
     assert_grad_close(gF1, gFa, "hit-dense deterministic vs atomic", mag=mF, wmag=mW)
-    np.testing.assert_array_equal(gp1, gpa)
+    assert_grad_close(gp1, ep, "hit-dense deterministic grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+    assert_grad_close(gpa, gp1, "hit-dense atomic vs deterministic grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
 
 
 def test_max_K_solid_scene(gpu_lib):

@@ -43,13 +43,18 @@ def test_noalloc_train_step_matches_workspace_entry_point(gpu_lib, precision):
             ref = _run(gpu_lib, case, o, d, t_rgb, t_dep, opts, False)
             got = _run(gpu_lib, case, o, d, t_rgb, t_dep, opts, True)
             assert np.count_nonzero(ref[3]) > 1000
-            # per-ray outputs, the loss and the decoder gradient are reduced in
-            # a fixed order: identical bits
-            for k in (0, 1, 2, 4):
+            # per-ray outputs: identical bits
+            for k in (0, 1):
                 assert np.array_equal(got[k].view(np.int32), ref[k].view(np.int32)), (n, flags, k)
             if flags:
-                assert np.array_equal(got[3].view(np.int32), ref[3].view(np.int32)), (n, flags)
+                # fixed-order reductions and a fixed item-to-block assignment:
+                # loss, feature and decoder gradients with identical bits
+                for k in (2, 3, 4):
+                    assert np.array_equal(got[k].view(np.int32), ref[k].view(np.int32)), (n, flags, k)
             else:
-                # feature gradients: FP32 atomics in any order
-                s = np.abs(ref[3]).max()
-                np.testing.assert_allclose(got[3], ref[3], rtol=1e-5, atol=1e-6 * s)
+                # feature gradients: FP32 atomics in any order; the loss and
+                # the decoder gradient: per-block partials of items handed
+                # out to whichever block is free
+                for k in (2, 3, 4):
+                    s = np.abs(ref[k]).max()
+                    np.testing.assert_allclose(got[k], ref[k], rtol=1e-5, atol=1e-6 * s)
