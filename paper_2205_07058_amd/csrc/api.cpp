@@ -363,9 +363,10 @@ int check_lf_model(const svlf_lf_model* m, const svlf_render_opts* opts, int64_t
 
 // Workspace: [hit slots][counts][per-hit state][dL/d(o_T0, o_T1)][decoder
 // packs][per-block partials of F_T][of F_C][per-block loss][BF16 calls with
-// a backward pass: the density decoder's input rows per hit slot]
+// a backward pass: the density decoder's input rows per hit slot][work-item
+// counters]
 struct LfLayout {
-  size_t hits, cnt, st, gT, packs, partT, partC, loss, xs, total;
+  size_t hits, cnt, st, gT, packs, partT, partC, loss, xs, ctr, total;
 };
 
 LfLayout lf_layout(int64_t n, int K, int precision, int viewdir, bool backward) {
@@ -392,6 +393,8 @@ LfLayout lf_layout(int64_t n, int K, int precision, int viewdir, bool backward) 
   w.xs = off;
   if (backward && precision == SVLF_BF16)
     off = align256(off + slots * static_cast<size_t>(lf_x_row()) * sizeof(uint16_t));
+  w.ctr = off;
+  off = align256(off + 3 * sizeof(int32_t));
   w.total = off;
   return w;
 }
@@ -430,6 +433,7 @@ int run_lf_call(int mode, const svlf_scene* scenes, int32_t n_scenes, const int6
   a.partT = reinterpret_cast<float*>(base + w.partT);
   a.partC = reinterpret_cast<float*>(base + w.partC);
   a.ws_loss = reinterpret_cast<float*>(base + w.loss);
+  a.item_counters = reinterpret_cast<int32_t*>(base + w.ctr);
   a.xsave = (need_grads && opts->precision == SVLF_BF16) ? reinterpret_cast<uint16_t*>(base + w.xs)
                                                          : nullptr;
   a.K = opts->K;

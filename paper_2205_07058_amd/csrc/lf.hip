@@ -266,6 +266,36 @@ extern __shared__ __attribute__((aligned(16))) char g_lds[];
 
 // Hit window: the rays of the item whose hits all fit in [s0, s0 + WIN);
 // returns s1 (end of the window) and publishes hit -> (ray lane | slot << 16).
+// Work items of a persistent light-field kernel: dealt round-robin over the
+// grid (the logical block index groups the blocks of one XCD), except the
+// last two rounds, which `counter` hands out in order to whichever block
+// asks first.  Uniform over the block; scr[10] carries the counter's value.
+struct ItemDeal {
+  int G, lb, nb, n_static;
+  int32_t* counter;
+  __device__ int first(int* scr) { return lb < n_static ? lb : tail(scr); }
+  __device__ int next(int item, int* scr) { return item + G < n_static ? item + G : tail(scr); }
+  __device__ int tail(int* scr) {
+    if (n_static == nb) return nb;
+    if (threadIdx.x == 0) scr[10] = n_static + atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = scr[10];
+    __syncthreads();
+    return it;
+  }
+};
+__device__ __forceinline__ ItemDeal item_deal(const LfArgs& a, int which) {
+  ItemDeal d;
+  d.G = gridDim.x;
+  const int b = blockIdx.x;
+  d.lb = (d.G % 8 == 0) ? (b % 8) * (d.G / 8) + b / 8 : b;
+  d.nb = a.tab.n_blocks;
+  d.counter = a.item_counters != nullptr ? a.item_counters + which : nullptr;
+  const int n_tail = d.counter != nullptr ? (d.nb < 2 * d.G ? d.nb : 2 * d.G) : 0;
+  d.n_static = d.nb - n_tail;
+  return d;
+}
+
 template <int WIN>
 __device__ __forceinline__ int open_window(int s0, int total, int off, int count, int* scr,
                                            int* hmap, bool& in_win) {
@@ -475,9 +505,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
 #pragma unroll
   for (int l = 0; l < M::NL; ++l) dbp[l] = 0.0f;
 
-  const int G = gridDim.x, bidx = blockIdx.x;
-  const int lb = (G % 8 == 0) ? (bidx % 8) * (G / 8) + bidx / 8 : bidx;
-  for (int item = lb; item < a.tab.n_blocks; item += G) {
+  ItemDeal deal = item_deal(a, CF::BWD ? 2 : 0);
+  for (int item = deal.first(scr); item < deal.nb; item = deal.next(item, scr)) {
     const DevScene& sc = a.tab.s[scene_of(a.tab, item)];
     const ItemRays ir = item_rays(sc, item);
     const int64_t r = ir.ray(tid);
@@ -868,9 +897,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
   for (int l = 0; l < M::NL; ++l) dbp[l] = 0.0f;
   float loss_acc = 0.0f;
 
-  const int G = gridDim.x, bidx = blockIdx.x;
-  const int lb = (G % 8 == 0) ? (bidx % 8) * (G / 8) + bidx / 8 : bidx;
-  for (int item = lb; item < a.tab.n_blocks; item += G) {
+  ItemDeal deal = item_deal(a, 1);
+  for (int item = deal.first(scr); item < deal.nb; item = deal.next(item, scr)) {
     const DevScene& sc = a.tab.s[scene_of(a.tab, item)];
     const int64_t zc = sc.n_vertices * kLfCT;       // Z_C follows Z_T
     const float* featC32 = sc.feat32 + zc;
@@ -1391,6 +1419,8 @@ hipError_t run_lf(const LfArgs& a, int mode, hipStream_t s) {
   hipLaunchKernelGGL((k_lf_pack<BF, VD>), dim3(64), dim3(kThreads), 0, s, a.params,
                      static_cast<char*>(a.packs));
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.item_counters != nullptr)
+    e = launch_fill(reinterpret_cast<float*>(a.item_counters), 0.0f, 3, s);   // 0.0f has zero bits
   if (e != hipSuccess) return e;
   int g1 = 0, g2 = 0, g3 = 0;
   const int fwd_cap = 4096, bwd_cap = lf_grid_limit();

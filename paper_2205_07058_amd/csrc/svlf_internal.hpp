@@ -189,6 +189,8 @@ struct LfArgs {
   float lambda_eta;       // staged losses: weight of (eta - eta_target)^2
   float lambda_tau;       // staged losses: weight of e^{-2 tau}
   int32_t freeze_color;   // nonzero: no gradients for Z_C and the colour decoder
+  int32_t* item_counters; // [3] zeroed before the kernels: density forward, colour,
+                          // density backward; each hands out its launch's last items
   float* partT;           // [grid][params_density]
   float* partC;           // [grid][params_color]
   float* ws_loss;         // [grid]
