@@ -494,12 +494,14 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
       return w1;
     };
     // Gather in three dependent stages: (A) hit records and rays, (B) the
-    // leaves' corner ids, (C) trilinear weights and the 8 corner rows -> X.
-    // A thread serves GRP hits (in the backward kernels one group covers the
-    // window).  There (PIPE) windows are opened one ahead and the next
-    // window's stage A is issued before this window's stage C, its stage B
-    // after the forward decoder, so that the gather waits on one level of
-    // loads only.
+    // leaves' corner ids, (C) the 8 corner rows (issued into registers, then
+    // consumed with the trilinear weights into X).  A thread serves GRP hits
+    // (in the backward kernels one group covers the window).  There (PIPE)
+    // windows are opened one ahead: the next window's stage A is issued
+    // before this window's rows are consumed, its stage B after the forward
+    // decoder and its stage C loads after the compositing, so that they are
+    // in flight while this window's backward runs; only an item's first
+    // window waits on all three.
     constexpr int ROWB = CF::C * CF::EB;
     constexpr int TPH = ROWB / 16;
     constexpr int VPT = 16 / CF::EB;             // values per thread
