@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "svlf_internal.hpp"
 
 namespace svlf {
@@ -151,6 +153,16 @@ int make_table(const svlf_scene* scenes, int n_scenes, const int64_t* offs, bool
   tab->n_blocks = static_cast<int32_t>(blocks);
   return SVLF_OK;
 }
+
+// A roctx range over one library call, named after its entry point:
+// `rocprofv3 --marker-trace` shows it around the call's kernels (without a
+// tracer attached the calls do nothing).
+struct CallRange {
+  explicit CallRange(const char* name) { roctxRangePush(name); }
+  ~CallRange() { roctxRangePop(); }
+  CallRange(const CallRange&) = delete;
+  CallRange& operator=(const CallRange&) = delete;
+};
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -497,6 +509,7 @@ int svlf_lf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ra
                    const float* ray_d, float* out_rgb, float* out_depth, float* out_acc,
                    void* workspace, size_t ws_bytes, void* stream) {
   const char* who = "svlf_lf_render";
+  const CallRange range(who);
   if (out_rgb == nullptr || out_depth == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "out_rgb / out_depth is NULL"));
   LfArgs a{};
@@ -514,6 +527,7 @@ int svlf_lf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
                             float* const* grad_features, float* grad_params, void* workspace,
                             size_t ws_bytes, void* stream) {
   const char* who = "svlf_lf_render_backward";
+  const CallRange range(who);
   if (grad_rgb == nullptr || grad_depth == nullptr || grad_params == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "grad_rgb / grad_depth / grad_params is NULL"));
   LfArgs a{};
@@ -533,6 +547,7 @@ int svlf_lf_train_stage(const svlf_scene* scenes, int32_t n_scenes,
                         float* loss_out, float* const* grad_features, float* grad_params,
                         void* workspace, size_t ws_bytes, void* stream) {
   const char* who = "svlf_lf_train_stage";
+  const CallRange range(who);
   if (loss == nullptr) return fail(SVLF_E_INVAL, who_str(who, "loss is NULL"));
   if (loss->kind != SVLF_LF_LOSS_SURFACE && loss->kind != SVLF_LF_LOSS_VOLUME)
     return fail(SVLF_E_RANGE, who_str(who, "unknown loss kind"));
@@ -566,6 +581,7 @@ int svlf_lf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t
                        float* const* grad_features, float* grad_params, void* workspace,
                        size_t ws_bytes, void* stream) {
   const char* who = "svlf_lf_train_step";
+  const CallRange range(who);
   if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
   if (!std::isfinite(lambda_depth) || !std::isfinite(loss_scale))
@@ -601,6 +617,7 @@ int svlf_build_octree_sizes(const int32_t* leaf_ijk_host, int64_t n, int32_t dep
 int svlf_build_octree(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
                       svlf_node* nodes_dev, int32_t* leaf_corners_dev,
                       int32_t* leaf_ijk_sorted_host, void* stream) {
+  const CallRange range("svlf_build_octree");
   HostOctree h;
   int rc = build_octree_host(leaf_ijk_host, n, depth, &h, true);
   if (rc) return rc;
@@ -624,6 +641,7 @@ int svlf_build_octree(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
 int svlf_build_octree_host(const int32_t* leaf_ijk_host, int64_t n, int32_t depth,
                            svlf_node* nodes_host, int32_t* leaf_corners_host,
                            int32_t* leaf_ijk_sorted_host) {
+  const CallRange range("svlf_build_octree_host");
   HostOctree h;
   int rc = build_octree_host(leaf_ijk_host, n, depth, &h, true);
   if (rc) return rc;
@@ -652,6 +670,7 @@ int svlf_occupancy_from_depth(const float* ray_o, const float* ray_d, const floa
                               int64_t* n_leaves_out, void* workspace, size_t ws_bytes,
                               void* stream) {
   const char* who = "svlf_occupancy_from_depth";
+  const CallRange range(who);
   if (level < 1 || level > SVLF_MAX_DEPTH)
     return fail(SVLF_E_RANGE, who_str(who, "level must be in [1, 10]"));
   if (n < 0) return fail(SVLF_E_INVAL, who_str(who, "n < 0"));
@@ -676,6 +695,7 @@ int svlf_trace_hits(const svlf_octree* oct, const float* ray_o, const float* ray
                     int64_t n_rays, int32_t K, int32_t* hit_leaf, float* hit_tin,
                     float* hit_tout, int32_t* hit_count, void* stream) {
   const char* who = "svlf_trace_hits";
+  const CallRange range(who);
   int rc = check_octree(oct, who);
   if (rc) return rc;
   if (n_rays < 0) return fail(SVLF_E_INVAL, who_str(who, "n_rays < 0"));
@@ -727,6 +747,7 @@ int svlf_render(const svlf_scene* scenes, int32_t n_scenes, const int64_t* ray_o
                 const float* ray_d, float* out_rgb, float* out_depth, float* out_acc,
                 void* workspace, size_t ws_bytes, void* stream) {
   const char* who = "svlf_render";
+  const CallRange range(who);
   if (out_rgb == nullptr || out_depth == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "out_rgb / out_depth is NULL"));
   ShadeArgs a{};
@@ -744,6 +765,7 @@ int svlf_render_backward(const svlf_scene* scenes, int32_t n_scenes,
                          float* const* grad_features, float* grad_params, void* workspace,
                          size_t ws_bytes, void* stream) {
   const char* who = "svlf_render_backward";
+  const CallRange range(who);
   if (grad_rgb == nullptr || grad_depth == nullptr || grad_params == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "grad_rgb / grad_depth / grad_params is NULL"));
   ShadeArgs a{};
@@ -762,6 +784,7 @@ int svlf_train_step(const svlf_scene* scenes, int32_t n_scenes, const int64_t* r
                     float* loss_out, float* const* grad_features, float* grad_params,
                     void* workspace, size_t ws_bytes, void* stream) {
   const char* who = "svlf_train_step";
+  const CallRange range(who);
   if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
   if (!std::isfinite(lambda_depth) || !std::isfinite(loss_scale))
@@ -787,6 +810,7 @@ int svlf_train_step_noalloc(const svlf_scene* scenes, int32_t n_scenes,
                             float* loss_out, float* const* grad_features, float* grad_params,
                             void* stream) {
   const char* who = "svlf_train_step_noalloc";
+  const CallRange range(who);
   if (target_rgb == nullptr || target_depth == nullptr || grad_params == nullptr)
     return fail(SVLF_E_INVAL, who_str(who, "targets / grad_params is NULL"));
   if (!std::isfinite(lambda_depth) || !std::isfinite(loss_scale))
@@ -808,6 +832,7 @@ int svlf_adam_step(float* param, float* grad, float* m, float* v, int64_t n, flo
                    float beta1, float beta2, float eps, int64_t step_t, uint16_t* bf16_out,
                    int32_t zero_grad, void* stream) {
   const char* who = "svlf_adam_step";
+  const CallRange range(who);
   if (n < 0) return fail(SVLF_E_INVAL, who_str(who, "n < 0"));
   if (step_t < 1) return fail(SVLF_E_RANGE, who_str(who, "step_t must be >= 1"));
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
@@ -829,6 +854,7 @@ int svlf_lazy_adam_step(float* param, float* grad, float* m, float* v, int64_t n
                         int32_t row_len, float lr, float beta1, float beta2, float eps,
                         int64_t step_t, uint16_t* bf16_out, int32_t zero_grad, void* stream) {
   const char* who = "svlf_lazy_adam_step";
+  const CallRange range(who);
   if (n_rows < 0) return fail(SVLF_E_INVAL, who_str(who, "n_rows < 0"));
   if (row_len < 4 || row_len > 256 || row_len % 4 != 0)
     return fail(SVLF_E_UNSUPPORTED, who_str(who, "row_len must be a multiple of 4 in [4, 256]"));
@@ -855,6 +881,7 @@ int svlf_lazy_adam_step(float* param, float* grad, float* m, float* v, int64_t n
 }
 
 int svlf_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream) {
+  const CallRange range("svlf_to_bf16");
   if (n < 0) return fail(SVLF_E_INVAL, "svlf_to_bf16: n < 0");
   if (n == 0) return SVLF_OK;
   if (src == nullptr || dst == nullptr) return fail(SVLF_E_INVAL, "svlf_to_bf16: NULL array");
@@ -864,6 +891,7 @@ int svlf_to_bf16(const float* src, uint16_t* dst, int64_t n, void* stream) {
 }
 
 int svlf_fill(float* dst, float value, int64_t n, void* stream) {
+  const CallRange range("svlf_fill");
   if (n < 0) return fail(SVLF_E_INVAL, "svlf_fill: n < 0");
   if (n == 0) return SVLF_OK;
   if (dst == nullptr) return fail(SVLF_E_INVAL, "svlf_fill: NULL array");
@@ -875,6 +903,7 @@ int svlf_fill(float* dst, float value, int64_t n, void* stream) {
 int svlf_mlp_forward(const svlf_mlp* mlp, const svlf_render_opts* opts, const float* X, int64_t n,
                      float* out, void* stream) {
   const char* who = "svlf_mlp_forward";
+  const CallRange range(who);
   int rc = check_opts(opts, who);
   if (rc) return rc;
   MlpShape sh;

@@ -46,7 +46,8 @@ def _build_sanitized():
         host_objs.append(obj)
     lib = os.path.join(OUT, "libsvlf_host_sanitized.so")
     _run(["g++", "-shared", "-fsanitize=address,undefined", "-o", lib] + host_objs + device_objs +
-         ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-lpthread"])
+         ["-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
+          "-lpthread"])
     return lib
 
 
@@ -59,7 +60,9 @@ def test_abi_and_host_octree_under_asan_ubsan():
     nm = _run(["nm", "-D", lib]).stdout
     assert "__asan_report" in nm and "__ubsan_handle" in nm, "sanitizers not linked"
     env = dict(os.environ)
-    env.update(SVLF_LIBRARY=lib, LD_PRELOAD=asan,
+    # the ASan runtime must come first; anything already preloaded stays
+    preload = asan + (":" + env["LD_PRELOAD"] if env.get("LD_PRELOAD") else "")
+    env.update(SVLF_LIBRARY=lib, LD_PRELOAD=preload,
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
