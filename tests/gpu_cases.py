@@ -33,9 +33,13 @@ Tolerances (FP32 path, derived from the arithmetic):
   one-sided derivatives).
 BF16 path: compared with the oracle's BF16-rounding mode; hidden activations
 may round differently where FP32 and FP64 accumulations straddle a bfloat16
-rounding boundary (one bfloat16 ulp = 2^-8 relative), so outputs are checked
-at max|err| <= 2^-6 max|ref| + 1e-4 S, and the error against the FP64 oracle
-is reported as PSNR.
+rounding boundary (one bfloat16 ulp = 2^-8 relative), so rendered outputs are
+checked at max|err| <= 2^-6 max|ref| + 1e-4 S, and the error against the FP64
+oracle is reported as PSNR.  The decoder alone is checked per entry
+(bf16_decoder_bound): each output within the error that FP32 accumulation
+can produce, carried through the layers, where a hidden activation may take
+the neighbouring bfloat16 value only if its exact pre-activation lies within
+that error of a rounding boundary.
 """
 
 import numpy as np
@@ -69,6 +73,37 @@ C_FEAT = 2.0 ** 8
 C_PARAM = 4.0
 C_W = 8.0          # single decoder: the midpoint's cell coordinates to a few ulps
 C_W_LF = 64.0      # light field: the surface point moves with eta's error
+
+
+def bf16_decoder_bound(params, widths, X):
+    """(ref, bound): the oracle's BF16-mode decoder outputs (n, out) and, per
+    entry, the largest |out - ref| of an implementation that rounds X, the
+    weights and every hidden activation to bfloat16 exactly as the oracle
+    does (to nearest, ties to even) but accumulates each dot product and its
+    bias in FP32 in any order.  The products of two bfloat16 values are exact
+    in FP32, so a layer's FP32 sum of n products and the bias is off by at
+    most gamma_n sum |terms| (gamma_n = n 2^-24 / (1 - n 2^-24)), plus
+    |W| times the error its inputs already carry.  ReLU and the rounding are
+    monotone, so a pre-activation known to within dz rounds to a value within
+    max(r(h(z + dz)) - r(h(z)), r(h(z)) - r(h(z - dz))) of the oracle's: zero
+    unless a rounding boundary lies within dz of z."""
+    from oracle.render import bf16_round as r
+    layers = split_params(params, widths)
+    a = r(np.asarray(X, np.float64))
+    e = np.zeros_like(a)
+    for li, (W, b) in enumerate(layers):
+        Wr = r(W)
+        absW = np.abs(Wr)
+        n = W.shape[1] + 1
+        gamma = 1.01 * n * EPS32 / (1.0 - n * EPS32)   # 1% covers the FP64 sum's own rounding
+        z = a @ Wr.T + b
+        dz = e @ absW.T + gamma * (np.abs(a) @ absW.T + np.abs(b))
+        if li == len(layers) - 1:
+            return z, dz
+        h = lambda v: r(np.maximum(v, 0.0))
+        a = h(z)
+        e = np.maximum(h(z + dz) - a, a - h(z - dz))
+    raise ValueError("empty MLP")
 
 
 def grad_error_ratio(got, exp, mag, unit=EPS32, wmag=None, c_w=C_W):

@@ -497,3 +497,50 @@ def test_bf16_round_matches_torch_conversion():
     x32 = x.astype(np.float32)
     ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float32).numpy()
     np.testing.assert_array_equal(bf16_round(x32.astype(np.float64)), ref.astype(np.float64))
+
+
+def _decoder_fp32_accumulation(p, widths, X, hidden=bf16_round, round_weights=True, serial=False):
+    """A BF16 decoder as a device would run it: bfloat16 operands, FP32 dot
+    products (numpy's FP32 matmul, or one product at a time in reverse order
+    with ``serial``), ``hidden`` applied to each ReLU output."""
+    from oracle.render import split_params
+    a = np.float32(bf16_round(np.asarray(X, np.float64)))
+    layers = split_params(p, widths)
+    for li, (W, b) in enumerate(layers):
+        Wr = np.float32(bf16_round(W) if round_weights else W)
+        if serial:
+            z = np.zeros((a.shape[0], W.shape[0]), np.float32)
+            for k in reversed(range(W.shape[1])):
+                z = z + a[:, k:k + 1] * Wr[:, k][None, :]
+            z = z + np.float32(b)
+        else:
+            z = a @ Wr.T + np.float32(b)
+        if li == len(layers) - 1:
+            return z.astype(np.float64)
+        a = np.float32(hidden(np.maximum(z.astype(np.float64), 0.0)))
+
+
+def _bf16_truncate(v):
+    m, e = np.frexp(v)
+    s = np.ldexp(1.0, 8 - np.maximum(e, -125))
+    return np.trunc(v * s) / s
+
+
+@pytest.mark.parametrize("widths", [(8, 32, 32, 4), (32, 64, 64, 64, 4)])
+def test_bf16_decoder_bound_holds_for_fp32_sums_and_catches_rounding_mistakes(widths):
+    """The per-entry bound the BF16 decoder parity test applies: met by FP32
+    accumulation in two summation orders, broken on most entries by hidden
+    activations truncated instead of rounded, left unrounded, or by weights
+    left in FP32."""
+    from tests.gpu_cases import bf16_decoder_bound
+    rng = np.random.default_rng(5)
+    p = xavier_params(rng, widths).astype(np.float64)
+    X = rng.normal(0, 0.5, (2000, widths[0])).astype(np.float32).astype(np.float64)
+    ref, bound = bf16_decoder_bound(p, widths, X)
+    np.testing.assert_array_equal(ref, mlp_forward(p, widths, X, bf16=True)[0])
+    assert np.median(bound) < 2e-4 * np.abs(ref).max()
+    for serial in (False, True):
+        assert np.all(np.abs(_decoder_fp32_accumulation(p, widths, X, serial=serial) - ref) <= bound)
+    for kw in ({"hidden": _bf16_truncate}, {"hidden": lambda v: v}, {"round_weights": False}):
+        out = _decoder_fp32_accumulation(p, widths, X, **kw)
+        assert np.mean(np.abs(out - ref) > bound) > 0.5, kw
