@@ -120,8 +120,10 @@ __device__ __forceinline__ void relu16(f32x16& t) {
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
 
 // Exclusive prefix sum of v over the block's NW waves (scr: NW ints of LDS).
-template <int NW>
-__device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total) {
+// `before_sync(prefix)` runs in every thread before the closing barrier, so
+// that LDS it writes is visible to the block when the scan returns.
+template <int NW, class F>
+__device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total, F&& before_sync) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int x = v;
 #pragma unroll
@@ -138,9 +140,14 @@ __device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total) {
     pre += (i < w) ? t : 0;
     tot += t;
   }
+  before_sync(pre + x - v);
   __syncthreads();
   total = tot;
   return pre + x - v;
+}
+template <int NW>
+__device__ __forceinline__ int block_excl_scan(int v, int* scr, int& total) {
+  return block_excl_scan<NW>(v, scr, total, [](int) {});
 }
 
 // Transposes the first ROWS columns of an LDS tile X [WIN][XS] (one row per

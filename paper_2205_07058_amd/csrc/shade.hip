@@ -41,6 +41,7 @@ using namespace detail;
 
 constexpr int kThreads = 256;
 static_assert(kThreads == kRaysPerBlock, "one ray per thread in a work item");
+static_assert(kThreads <= 256 && SVLF_MAX_K <= 256, "hit map entries: 8-bit lane, 8-bit slot");
 constexpr int kWaves = 4;
 
 // ------------------------------------------------------------ geometry
@@ -118,12 +119,19 @@ struct Cfg {
   static constexpr int L_OUT = align16(L_X + WIN * XS * EB);
   static constexpr int L_GZ = align16(L_OUT + WIN * 32);
   static constexpr int L_AT = align16(L_GZ + (BWD ? TROWS * TS * EB : 0));
+  // hit map: all of a work item's hits, 16 bits per hit (IMAP: backward
+  // kernels where it fits), else the window's hits, 32 bits per hit
+  // (backward: two windows, the current one and the next)
   static constexpr int L_MAP = align16(L_AT + (BWD ? TROWS * TS * EB : 0));
-  // backward: records of the window awaiting its scatter, the next window's
-  // hit map
-  static constexpr int L_REC2 = align16(L_MAP + WIN * 4);
-  static constexpr int L_MAP2 = align16(L_REC2 + (BWD ? WIN * 64 : 0));
-  static constexpr int L_SCR = align16(L_MAP2 + (BWD ? WIN * 4 : 0));
+  static constexpr int map_end(int entries) {
+    return align16(align16(L_MAP + entries * 2) + (BWD ? WIN * 64 : 0)) + 64;
+  }
+  static constexpr bool IMAP = BWD && map_end(kThreads * SVLF_MAX_K) <= 160 * 1024;
+  using MapT = typename std::conditional<IMAP, uint16_t, int32_t>::type;
+  static constexpr int MAP_ENTRIES = IMAP ? kThreads * SVLF_MAX_K : (BWD ? 2 : 1) * WIN;
+  // backward: records of the window awaiting its scatter
+  static constexpr int L_REC2 = align16(L_MAP + MAP_ENTRIES * static_cast<int>(sizeof(MapT)));
+  static constexpr int L_SCR = align16(L_REC2 + (BWD ? WIN * 64 : 0));
   static constexpr int LDS_BYTES = L_SCR + 64;
   static_assert(NBIAS <= kThreads, "one thread per bias entry writes its combined gradient");
   static_assert(C <= 32 && CI <= TROWS, "feature gradients come from one 32-row tile");
@@ -163,8 +171,9 @@ struct Smem {
   __device__ __forceinline__ typename CF::Elem* GZ() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_GZ); }
   __device__ __forceinline__ typename CF::Elem* AT() const { return reinterpret_cast<typename CF::Elem*>(g_smem + CF::L_AT); }
   __device__ __forceinline__ int* scr() const { return reinterpret_cast<int*>(g_smem + CF::L_SCR); }
-  __device__ __forceinline__ int* hmap(int b) const {
-    return reinterpret_cast<int*>(g_smem + (b ? CF::L_MAP2 : CF::L_MAP));
+  // entry = the hit's ray lane | (its slot in the ray's hit list << 8)
+  __device__ __forceinline__ typename CF::MapT* hmap() const {
+    return reinterpret_cast<typename CF::MapT*>(g_smem + CF::L_MAP);
   }
 };
 
@@ -473,25 +482,44 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     const float h = __int_as_float((128 - sc.depth) << 23);       // 2^(1-depth)
     const float inv_h = __int_as_float((126 + sc.depth) << 23);   // 2^(depth-1)
     int total;
-    const int off = block_excl_scan<kWaves>(count, sm.scr(), total);
+    // with IMAP all of the item's hits are mapped (hit -> ray lane, slot)
+    // once, as part of the scan
+    const int off = block_excl_scan<kWaves>(count, sm.scr(), total, [&](int o) {
+      if constexpr (CF::IMAP)
+        for (int q = 0; q < count; ++q) sm.hmap()[o + q] = static_cast<typename CF::MapT>(tid | (q << 8));
+    });
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, acc = 0.0f;
 
-    // Window: the rays whose hits all fit in [w0, w0 + WIN); the ray's lane
-    // alone publishes its map entries (window hit -> ray lane, slot) into
-    // hit map `hb`.  Returns the window's end; `inw` = this ray is in it.
+    // Window: the rays whose hits all fit in [w0, w0 + WIN).  Returns the
+    // window's end; `inw` = this ray is in it.  With the item's map the end
+    // is the start of the ray that holds hit w0 + WIN (no ray is longer than
+    // a window), read without a barrier; otherwise the ray's lane alone
+    // publishes its map entries into window map `hb`.
     auto open_win = [&](int w0, int hb, bool& inw) -> int {
-      if (tid == 0) sm.scr()[8] = total;
-      __syncthreads();
-      const bool started = count > 0 && off >= w0;
-      inw = started && off + count <= w0 + CF::WIN;
-      if (started && !inw) atomicMin(&sm.scr()[8], off);
-      __syncthreads();
-      const int w1 = sm.scr()[8];
-      if (inw) {
-        for (int q = 0; q < count; ++q) sm.hmap(hb)[off - w0 + q] = tid | (q << 16);
+      if constexpr (CF::IMAP) {
+        const int p = w0 + CF::WIN;
+        const int w1 = p < total ? p - (sm.hmap()[p] >> 8) : total;
+        inw = count > 0 && off >= w0 && off + count <= w1;
+        return w1;
+      } else {
+        if (tid == 0) sm.scr()[8] = total;
+        __syncthreads();
+        const bool started = count > 0 && off >= w0;
+        inw = started && off + count <= w0 + CF::WIN;
+        if (started && !inw) atomicMin(&sm.scr()[8], off);
+        __syncthreads();
+        const int w1 = sm.scr()[8];
+        if (inw) {
+          for (int q = 0; q < count; ++q)
+            sm.hmap()[hb * CF::WIN + off - w0 + q] = static_cast<typename CF::MapT>(tid | (q << 8));
+        }
+        __syncthreads();
+        return w1;
       }
-      __syncthreads();
-      return w1;
+    };
+    // map entry of hit hh of the window starting at w0 (map `hb`)
+    auto map_at = [&](int w0, int hb, int hh) -> int {
+      return sm.hmap()[CF::IMAP ? w0 + hh : hb * CF::WIN + hh];
     };
     // Gather in three dependent stages: (A) hit records and rays, (B) the
     // leaves' corner ids, (C) the 8 corner rows (issued into registers, then
@@ -523,15 +551,15 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     // one window's raw rows: filled for the next window after this one's
     // compositing, consumed when the next window starts
     Raw raw[GRP][8];
-    auto stage_a = [&](Stage& st, int pb, int hb, int twin) {
+    auto stage_a = [&](Stage& st, int pb, int w0, int hb, int twin) {
 #pragma unroll
       for (int k = 0; k < GRP; ++k) {
         st.hh[k] = (pb + k) * HPP + tid / TPH;
         st.val[k] = st.hh[k] < twin;
         if (st.val[k]) {
-          const int mp = sm.hmap(hb)[st.hh[k]];
-          const int64_t rr = ir.ray(mp & 0xFFFF);
-          st.hr[k] = a.hits[rr * a.K + (mp >> 16)];
+          const int mp = map_at(w0, hb, st.hh[k]);
+          const int64_t rr = ir.ray(mp & 0xFF);
+          st.hr[k] = a.hits[rr * a.K + (mp >> 8)];
           st.ro[k][0] = a.o[3 * rr]; st.ro[k][1] = a.o[3 * rr + 1]; st.ro[k][2] = a.o[3 * rr + 2];
           st.rd[k][0] = a.d[3 * rr]; st.rd[k][1] = a.d[3 * rr + 1]; st.rd[k][2] = a.d[3 * rr + 2];
         }
@@ -636,7 +664,7 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
     };
 
     Stage cur, nxt;
-    int hb = 0;                    // hit map of the current window
+    int hb = 0;                    // window map of the current window (without IMAP)
     bool have_next = false;        // nxt holds stages A and B of the next window
     bool in_win_n = false;
     int s1n = 0;
@@ -656,16 +684,16 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
       if (pre) s1n = open_win(s1, hb ^ 1, in_win_n);
       if (PIPE) {
         if (!have_next) {
-          stage_a(cur, 0, hb, tw);
+          stage_a(cur, 0, s0, hb, tw);
           stage_b(cur);
           stage_c_issue(cur);
         }
-        if (pre) stage_a(nxt, 0, hb ^ 1, s1n - s1);
+        if (pre) stage_a(nxt, 0, s1, hb ^ 1, s1n - s1);
         stage_c_consume(cur);
       } else {
 #pragma unroll 1
         for (int pb = 0; pb < NPASS; pb += GRP) {
-          stage_a(cur, pb, hb, tw);
+          stage_a(cur, pb, s0, hb, tw);
           stage_b(cur);
           stage_c(cur);
         }
@@ -885,9 +913,8 @@ __global__ __launch_bounds__(kThreads, CF::BWD ? 1 : 3) void k_shade(ShadeArgs a
               const int hh = n0 + k + hs;
               if (hh < tw) {
                 const RecL rc = sm.rec(rb)[hh];
-                const int mp = sm.hmap(hb)[hh];
-                const int64_t slot =
-                    ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
+                const int mp = map_at(s0, hb, hh);
+                const int64_t slot = ir.ray(mp & 0xFF) * a.K + (mp >> 8);
                 float* rec_out = a.gxu + slot * (CF::C + 4);
                 rec_out[4 + c] = gxs[hh * CF::C + c];
                 if (c < 3) rec_out[c] = c == 0 ? rc.ux : (c == 1 ? rc.uy : rc.uz);
