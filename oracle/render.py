@@ -236,7 +236,52 @@ def render_backward(st, grad_rgb, grad_depth, grad_acc=None):
     return grad_F, grad_params
 
 
-def render_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None):
+def sigma_output_term_magnitude(st, grad_rgb, grad_depth, grad_acc=None):
+    """Per hit, the sum of absolute values of the terms that make up dL/do_3
+    (the decoder's density output; test infrastructure).  Eq. 3's backward
+    gives dL/dtau = sum_ch g_ch (T_next c_ch - S_ch) + g_d (T_next t - S_t)
+    + g_a (T_next - S_a) with S the suffix sums over the ray's later hits;
+    on a ray with many hits these terms nearly cancel, and another
+    evaluation of dL/dtau is accurate to their size, not to its own.
+    G = sum_ch |g_ch| (T_next c_ch + S_ch) + |g_d| (T_next t + S_t) +
+    |g_a| (T_next + S_a), times dtau where o_3 > 0.  Returns (m,)."""
+    n = st.n
+    g_rgb = np.asarray(grad_rgb, np.float64).reshape(n, 3)
+    g_d = np.asarray(grad_depth, np.float64).reshape(n)
+    g_a = np.zeros(n) if grad_acc is None else np.asarray(grad_acc, np.float64).reshape(n)
+    T, w, tau, col, tmid = st.T, st.w, st.tau, st.col, st.tmid
+    T_next = T * np.exp(-tau)
+    wc = w[:, :, None] * col
+    S_c = np.sum(wc, axis=1, keepdims=True) - np.cumsum(wc, axis=1)
+    wt = w * tmid
+    S_t = np.sum(wt, axis=1, keepdims=True) - np.cumsum(wt, axis=1)
+    S_a = np.sum(w, axis=1, keepdims=True) - np.cumsum(w, axis=1)
+    G = (np.sum(np.abs(g_rgb)[:, None, :] * (T_next[:, :, None] * col + S_c), axis=2)
+         + np.abs(g_d)[:, None] * (T_next * np.abs(tmid) + np.abs(S_t)) + np.abs(g_a)[:, None] * (T_next + S_a))
+    G = G[st.ray_i, st.slot_i] * st.dtau
+    return np.where(st.out[:, 3] > 0.0, G, 0.0)
+
+
+def decoder_input_jacobian(st):
+    """Per hit, d o_k / d X for each of the decoder's 4 outputs (the feature
+    part of the input; the hit's ReLU pattern; bfloat16 weights in the BF16
+    mode).  Returns (m, 4, C)."""
+    layers = split_params(st.params, st.widths)
+    r = bf16_round if st.bf16 else (lambda v: v)
+    m = st.out.shape[0]
+    J = np.zeros((m, 4, st.C))
+    for k in range(4):
+        g_z = np.zeros((m, 4))
+        g_z[:, k] = 1.0
+        for li in range(len(layers) - 1, -1, -1):
+            g_a = g_z @ r(layers[li][0])
+            if li > 0:
+                g_z = np.where(st.pres[li - 1] > 0.0, g_a, 0.0)
+        J[:, k, :] = g_a[:, :st.C]
+    return J
+
+
+def render_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None, conditioned=False):
     """Scale of the per-hit contributions behind every entry of
     ``render_backward`` (test infrastructure: the scale of per-entry rounding
     bounds of another evaluation of the same sums).
@@ -252,8 +297,11 @@ def render_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None):
           biases: max_i |dL/dz_h[i]|).
     S bounds the entry (triangle inequality), also when the hits' terms
     cancel; R is the scale of a hit's own evaluation error, which arises
-    over the whole group (the decoder backward mixes all its units).
-    Returns (M_features (n_vertices, C), M_params)."""
+    over the whole group (the decoder backward mixes all its units).  With
+    ``conditioned`` a hit's dL/dX is taken at its conditioning,
+    sum_{k<3} |J_k| |dL/do_k| + |J_3| G (``decoder_input_jacobian``,
+    ``sigma_output_term_magnitude``), in place of its absolute value, for the
+    feature entries.  Returns (M_features (n_vertices, C), M_params)."""
     per_layer, g_X = _backward_per_hit(st, grad_rgb, grad_depth, grad_acc)
     mags = []
     for g_zr, a in per_layer:
@@ -263,6 +311,11 @@ def render_backward_hit_magnitude(st, grad_rgb, grad_depth, grad_acc=None):
         mags.append(np.concatenate([(gz.T @ aa).ravel() + rW, np.sum(gz, axis=0) + rb]))
     M_params = np.concatenate(mags)
     gx = np.abs(g_X)
+    if conditioned:
+        J = np.abs(decoder_input_jacobian(st))
+        g_out = np.abs(per_layer[-1][0])
+        G = sigma_output_term_magnitude(st, grad_rgb, grad_depth, grad_acc)
+        gx = np.einsum("mkc,mk->mc", J[:, :3, :], g_out[:, :3]) + J[:, 3, :] * G[:, None]
     row = st.wj[:, :, None] * (gx[:, None, :] + gx.max(axis=1, initial=0.0)[:, None, None])
     M_F = np.zeros((st.n_vertices, st.C))
     np.add.at(M_F, st.corners.ravel(), row.reshape(-1, st.C))

@@ -15,9 +15,10 @@ import numpy as np
 import pytest
 
 from oracle.octree import Octree
-from oracle.render import (bf16_round, interpolation_weights, loss, mlp_forward,
+from oracle.render import (bf16_round, decoder_input_jacobian, interpolation_weights, loss, mlp_forward,
                            render, render_backward, render_backward_hit_magnitude,
-                           render_backward_weight_scale, split_params, weight_sensitivity)
+                           render_backward_weight_scale, sigma_output_term_magnitude, split_params,
+                           weight_sensitivity)
 from oracle.trace import trace_hits
 from synth.configs import param_count, tiny_workload, xavier_params
 from tests.helpers import crafted_occupancy, random_rays
@@ -426,6 +427,76 @@ def test_hit_magnitude_adds_over_cancelling_hits():
     np.testing.assert_allclose(m2F, 2 * m1F, rtol=1e-13, atol=0)
     np.testing.assert_allclose(m2p, 2 * m1p, rtol=1e-13, atol=0)
     assert m1F.max() > 0 and m1p.max() > 0
+
+
+def test_conditioned_magnitude_bounds_and_contains_the_plain_one():
+    """The conditioned scale of the feature entries bounds every entry, is
+    at least the plain one (|J_k| |g_k| sums dominate |sum J_k g_k|), scales
+    linearly with the upstream gradients and ignores their sign; the
+    decoder-parameter scale is unchanged."""
+    oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
+    rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits)
+    rng = np.random.default_rng(3)
+    ups = [rng.normal(size=rgb.shape), rng.normal(size=dep.shape), rng.normal(size=acc.shape)]
+    gF, _ = render_backward(st, *ups)
+    mF, mp = render_backward_hit_magnitude(st, *ups)
+    cF, cp = render_backward_hit_magnitude(st, *ups, conditioned=True)
+    assert np.all(cF >= np.abs(gF)) and np.all(cF >= mF * (1 - 1e-12))
+    np.testing.assert_array_equal(cp, mp)
+    cF2, _ = render_backward_hit_magnitude(st, *[-2 * u for u in ups], conditioned=True)
+    np.testing.assert_allclose(cF2, 2 * cF, rtol=1e-14, atol=0)
+
+
+def test_decoder_input_jacobian_against_finite_differences():
+    oc, F, p, widths, o, d, hits, _, _ = _fd_setup(12)
+    _, _, _, st = render(oc, F, p, widths, o, d, hits)
+    J = decoder_input_jacobian(st)
+    X = st.X[:20]
+    eps = 1e-6
+    for c in range(st.C):
+        e = np.zeros_like(X)
+        e[:, c] = eps
+        fd = (mlp_forward(p, widths, X + e)[0] - mlp_forward(p, widths, X - e)[0]) / (2 * eps)
+        np.testing.assert_allclose(J[:20, :, c], fd, rtol=1e-6, atol=1e-8)
+
+
+def test_sigma_term_magnitude_one_hit_and_cancellation():
+    """One hit with only an opacity gradient: dL/dtau is a single term, so G
+    equals |dL/do_3| and the conditioned scale equals the plain one.  Upstream
+    gradients chosen so that the first hit's dL/dtau cancels exactly: its
+    dL/do_3 is zero but G is not (another evaluation of the same terms is off
+    by their size)."""
+    oc, F, p, widths, o, d, _, _, _ = _fd_setup(12)
+    hits = trace_hits(oc, o, d, 1)
+    r = int(np.nonzero(hits[3] > 0)[0][0])
+    h1 = tuple(x[r:r + 1] for x in hits)
+    _, _, _, st = render(oc, F, p, widths, o[r:r + 1], d[r:r + 1], h1)
+    assert st.out[0, 3] > 0
+    ups = [np.zeros((1, 3)), np.zeros(1), np.array([-0.7])]
+    T_next = st.T[0, 0] * np.exp(-st.tau[0, 0])
+    G = sigma_output_term_magnitude(st, *ups)
+    np.testing.assert_allclose(G, [0.7 * T_next * st.dtau[0]], rtol=1e-14)
+    mF, _ = render_backward_hit_magnitude(st, *ups)
+    cF, _ = render_backward_hit_magnitude(st, *ups, conditioned=True)
+    np.testing.assert_allclose(cF, mF, rtol=1e-12, atol=0)
+    # a ray with several hits; g_acc solves dL/dtau = 0 for its first hit
+    hits = trace_hits(oc, o, d, 4)
+    r = int(np.nonzero(hits[3] >= 3)[0][0])
+    h1 = tuple(x[r:r + 1] for x in hits)
+    _, _, _, st = render(oc, F, p, widths, o[r:r + 1], d[r:r + 1], h1)
+    g_rgb = np.array([[0.5, -0.3, 0.8]])
+    T_next = st.T[0] * np.exp(-st.tau[0])
+    wc = st.w[0][:, None] * st.col[0]
+    S_c = wc.sum(axis=0) - np.cumsum(wc, axis=0)
+    S_a = st.w[0].sum() - np.cumsum(st.w[0])
+    num = np.sum(g_rgb[0] * (T_next[0] * st.col[0, 0] - S_c[0]))
+    ups = [g_rgb, np.zeros(1), np.array([-num / (T_next[0] - S_a[0])])]
+    from oracle.render import _backward_per_hit
+    per_layer, _ = _backward_per_hit(st, *ups)
+    g3 = per_layer[-1][0][:, 3]
+    G = sigma_output_term_magnitude(st, *ups)
+    assert st.out[0, 3] > 0 and G[0] > 0 and abs(g3[0]) <= 1e-12 * G[0]
+    assert np.all(G >= np.abs(g3) * (1 - 1e-12))
 
 
 def test_weight_sensitivity_against_finite_differences_and_closed_forms():
