@@ -493,3 +493,70 @@ def test_depth_10_scene(gpu_lib):
     lmW = render_lf_backward_weight_scale(lst, lg_rgb, lg_dep)
     assert_grad_close(lgF, leF, "depth 10 lf grad_features", mag=lmF, wmag=lmW, c_w=C_W_LF)
     assert_grad_close(lgp, lep, "depth 10 lf grad_params", rel_nw=1e-4, mag=lmp, c=C_PARAM)
+
+
+def _train_outputs(case, o, d, t_rgb, t_dep, precision):
+    import torch
+    n = o.shape[0]
+    to, td = case.rays(o, d)
+    gF = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+    gp = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+    loss_t = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out_rgb = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    out_dep = torch.empty((n,), dtype=torch.float32, device="cuda")
+    case.svlf.train_step([case.scene], [n], case.params, case.widths, case.opts(precision), to, td,
+                         torch.from_numpy(t_rgb).cuda(), torch.from_numpy(t_dep).cuda(),
+                         0.1, 1.0 / n, [gF], gp, out_rgb, out_dep, loss_t)
+    torch.cuda.synchronize()
+    return out_rgb.cpu().numpy(), out_dep.cpu().numpy(), float(loss_t.item())
+
+
+def test_full_items_of_max_hits(gpu_lib):
+    """A fully occupied depth-5 scene crossed by rays through its centre:
+    every ray keeps K = 16 hits, so each full 256-ray work item holds the
+    largest possible hit list (4,096 hits, 32 windows) and its windows end
+    where the item's hit map ends.  Train-step outputs and loss on every ray
+    (two full items and a ragged one, FP32 and BF16), and the gradients on
+    the rays clear of decoder kinks, against the oracle."""
+    from tests.helpers import crafted_occupancy
+    leaves = crafted_occupancy("full", 5).astype(np.int32)
+    widths = (16, 64, 64, 64, 4)
+    rng = np.random.default_rng(77)
+    F = (rng.normal(0.0, 1.0, (33 ** 3, 16)) * 2.0).astype(np.float32)
+    p = xavier_params(rng, widths)
+    p[-1] = 0.0                        # mean opacity about 0.4 over the 16 voxels
+    case = Case(gpu_lib, leaves, 5, F, p, widths, 16)
+    n = 2 * 256 + 37
+    v = rng.standard_normal((n, 3))
+    o = (3.0 * v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    d = rng.uniform(-0.2, 0.2, (n, 3)) - o
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    er, ed, ea, st = case.oracle(o, d)
+    counts = np.bincount(st.ray_i, minlength=n)
+    assert np.all(counts == 16), np.bincount(counts)
+    t_rgb = rng.uniform(0, 1, (n, 3)).astype(np.float32)
+    t_dep = rng.uniform(0, 5, n).astype(np.float32)
+    rgb, dep, L = _train_outputs(case, o, d, t_rgb, t_dep, "fp32")
+    L_ref, _, _ = oracle_loss(er, ed, t_rgb, t_dep, 0.1)
+    assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
+    assert_outputs_close(rgb, er, 1.0, "full items rgb")
+    assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), "full items depth")
+    br, bd, _, _ = case.oracle(o, d, bf16=True)
+    rgb16, dep16, _ = _train_outputs(case, o, d, t_rgb, t_dep, "bf16")
+    S = max(1.0, np.abs(bd).max())
+    assert np.abs(rgb16 - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4
+    assert np.abs(dep16 - bd).max() <= 2 ** -6 * S + 1e-4 * S
+    keep = case.smooth_rays(o, d)
+    assert keep.size > n // 3
+    g_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)
+    g_dep = rng.normal(size=keep.size).astype(np.float32)
+    gF, gp = _gpu_backward(case, o[keep], d[keep], g_rgb, g_dep, None)
+    _, _, _, st2 = case.oracle(o[keep], d[keep])
+    eF, ep = render_backward(st2, g_rgb, g_dep)
+    # 16 hits on every ray: Eq. 3's dL/dtau is a difference of suffix sums
+    # over up to 15 later hits, so the feature entries are checked at the
+    # conditioning of each hit's dL/dX
+    mF, mp = render_backward_hit_magnitude(st2, g_rgb, g_dep, conditioned=True)
+    mW = render_backward_weight_scale(st2, g_rgb, g_dep)
+    assert_grad_close(gF, eF, "full items grad_features", mag=mF, wmag=mW)
+    assert_grad_close(gp, ep, "full items grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
