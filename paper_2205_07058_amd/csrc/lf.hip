@@ -313,6 +313,18 @@ __device__ __forceinline__ int open_window(int s0, int total, int off, int count
   return s1;
 }
 
+// The same window from a map of all of the item's hits (hit -> lane |
+// slot << 16, written once per item): the window ends at the start of the
+// ray that holds hit s0 + WIN (no ray is longer than a window).  No barrier.
+template <int WIN>
+__device__ __forceinline__ int open_window_imap(int s0, int total, int off, int count,
+                                                const int* imap, bool& in_win) {
+  const int p = s0 + WIN;
+  const int s1 = p < total ? p - (imap[p] >> 16) : total;
+  in_win = count > 0 && off >= s0 && off + count <= s1;
+  return s1;
+}
+
 __device__ __forceinline__ int scene_of(const SceneTable& tab, int item) {
   int si = 0;
   while (si + 1 < tab.n && item >= tab.s[si + 1].block_begin) ++si;
@@ -415,7 +427,9 @@ struct DCfg {
   static constexpr int L_GZ = align16(L_X + WIN * XS * EB);
   static constexpr int L_AT = align16(L_GZ + (BWD ? kLfH * TS * EB : 0));
   static constexpr int L_MAP = align16(L_AT + (BWD ? XT_ROWS * TS * EB : 0));
-  static constexpr int L_SCR = align16(L_MAP + WIN * 4);
+  // hit map: all of a work item's hits (IMAP: backward, where it fits) or the window's
+  static constexpr bool IMAP = BWD && align16(L_MAP + kThreads * SVLF_MAX_K * 4) + 64 <= 160 * 1024;
+  static constexpr int L_SCR = align16(L_MAP + (IMAP ? kThreads * SVLF_MAX_K : WIN) * 4);
   static constexpr int LDS = L_SCR + 64;
   static_assert(LDS <= 160 * 1024, "LDS");
   static_assert(!BWD || WIN * 2 * kLfCT * 4 <= L_MAP - L_GZ, "dL/dz staging fits in GZ + AT");
@@ -514,10 +528,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
     const float h = __int_as_float((128 - sc.depth) << 23);
     const float inv_h = __int_as_float((126 + sc.depth) << 23);
     int total;
-    const int off = block_excl_scan<kWaves>(count, scr, total);
+    const int off = block_excl_scan<kWaves>(count, scr, total, [&](int o) {
+      if constexpr (CF::IMAP)
+        for (int q = 0; q < count; ++q) hmap[o + q] = tid | (q << 16);
+    });
     for (int s0 = 0; s0 < total;) {
       bool in_win;
-      const int s1 = open_window<CF::WIN>(s0, total, off, count, scr, hmap, in_win);
+      const int s1 = CF::IMAP ? open_window_imap<CF::WIN>(s0, total, off, count, hmap, in_win)
+                              : open_window<CF::WIN>(s0, total, off, count, scr, hmap, in_win);
+      const int* wmap = CF::IMAP ? hmap + s0 : hmap;    // the window's map entries
       const int tw = s1 - s0;
       (void)in_win;
       if (BF && CF::BWD && a.xsave != nullptr) {
@@ -525,7 +544,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
         // hit rebuilds its record, the rows stream back 16 B per thread
         for (int hh = tid; hh < CF::WIN; hh += kThreads) {
           if (hh < tw) {
-            const int mp = hmap[hh];
+            const int mp = wmap[hh];
             const int64_t ray = ir.ray(mp & 0xFFFF);
             const HitRec hr = a.hits[ray * a.K + (mp >> 16)];
             const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
@@ -553,7 +572,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           const int hh = e / CPR, c = e % CPR;
           uint4 v = make_uint4(0u, 0u, 0u, 0u);
           if (hh < tw) {
-            const int mp = hmap[hh];
+            const int mp = wmap[hh];
             const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
             v = *reinterpret_cast<const uint4*>(a.xsave + slot * M::IN0P + 8 * c);
           }
@@ -573,7 +592,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
           for (int i = 0; i < VPT; ++i) v1[i] = v2[i] = 0.0f;
           float rr[6] = {0, 0, 0, 0, 0, 0};
           if (hh < tw) {
-            const int mp = hmap[hh];
+            const int mp = wmap[hh];
             const int64_t ray = ir.ray(mp & 0xFFFF);
             const HitRec hr = a.hits[ray * a.K + (mp >> 16)];
             const float ox = a.o[3 * ray], oy = a.o[3 * ray + 1], oz = a.o[3 * ray + 2];
@@ -647,7 +666,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
         constexpr int CPR = M::IN0P * 2 / 16;
         for (int e = tid; e < tw * CPR; e += kThreads) {
           const int hh = e / CPR, c = e % CPR;
-          const int mp = hmap[hh];
+          const int mp = wmap[hh];
           const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
           *reinterpret_cast<uint4*>(a.xsave + slot * M::IN0P + 8 * c) =
               *reinterpret_cast<const uint4*>(dX<CF>() + hh * CF::XS + 8 * c);
@@ -692,7 +711,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
         if (has_tile && g == 0 && n0 + lane < tw) {
           const int hh = n0 + lane;
           const DRec rc = rec[hh];
-          const int mp = hmap[hh];
+          const int mp = wmap[hh];
           const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
           const float dt = rc.tout - rc.tin;
           const float ft = a.tau_mode == SVLF_TAU_VOXEL ? dt * inv_h
@@ -718,7 +737,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_density(LfArgs a) {
 #pragma unroll
         for (int mt = 0; mt < M::MTH; ++mt) gz[mt] = zero16();
         if (has_tile && g == 0 && n0 + lane < tw) {
-          const int mp = hmap[n0 + lane];
+          const int mp = wmap[n0 + lane];
           const int64_t slot = ir.ray(mp & 0xFFFF) * a.K + (mp >> 16);
           const float2 gv = *reinterpret_cast<const float2*>(a.gT + 2 * slot);
           gz[0][0] = gv.x;
@@ -848,7 +867,9 @@ struct CCfg {
   static constexpr int L_XT = align16(L_ACT + (BWD ? ACT_ROWS * TS * EB : 0));
   static constexpr int L_GZ = align16(L_XT + ((BWD && !ACT_REG) ? XT_ROWS * TS * EB : 0));
   static constexpr int L_MAP = align16(L_GZ + (BWD ? kLfH * TS * EB : 0));
-  static constexpr int L_SCR = align16(L_MAP + WIN * 4);
+  // hit map: all of a work item's hits (IMAP: backward, where it fits) or the window's
+  static constexpr bool IMAP = BWD && align16(L_MAP + kThreads * SVLF_MAX_K * 4) + 64 <= 160 * 1024;
+  static constexpr int L_SCR = align16(L_MAP + (IMAP ? kThreads * SVLF_MAX_K : WIN) * 4);
   static constexpr int LDS = L_SCR + 64;
   static_assert(LDS <= 160 * 1024, "LDS");
   static_assert(!BWD || WIN * kLfCC * 4 <= kLfH * TS * EB, "dL/dz_C staging fits in GZ");
@@ -911,11 +932,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
     const float h = __int_as_float((128 - sc.depth) << 23);
     const float inv_h = __int_as_float((126 + sc.depth) << 23);
     int total;
-    const int off = block_excl_scan<kWaves>(count, scr, total);
+    const int off = block_excl_scan<kWaves>(count, scr, total, [&](int o) {
+      if constexpr (CF::IMAP)
+        for (int q = 0; q < count; ++q) hmap[o + q] = tid | (q << 16);
+    });
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, acc = 0.0f;
     for (int s0 = 0; s0 < total;) {
       bool in_win;
-      const int s1 = open_window<CF::WIN>(s0, total, off, count, scr, hmap, in_win);
+      const int s1 = CF::IMAP ? open_window_imap<CF::WIN>(s0, total, off, count, hmap, in_win)
+                              : open_window<CF::WIN>(s0, total, off, count, scr, hmap, in_win);
+      const int* wmap = CF::IMAP ? hmap + s0 : hmap;    // the window's map entries
       const int tw = s1 - s0;
       {
         constexpr int TPH = kLfCC * CF::EB / 16;
@@ -929,7 +955,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
           for (int i = 0; i < VPT; ++i) v[i] = 0.0f;
           float rr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
           if (hh < tw) {
-            const int mp = hmap[hh];
+            const int mp = wmap[hh];
             const int64_t ray = ir.ray(mp & 0xFFFF);
             const int64_t slot = ray * a.K + (mp >> 16);
             const HitRec hr = a.hits[slot];
@@ -1329,7 +1355,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_color(LfArgs a) {
               }
               const float* hp = out + 8 * hh;
               const float g_eta = (rc.tin - rc.tout) * (hp[4] + gx_d * inv_h) + hp[5];
-              const int mp = hmap[hh];
+              const int mp = wmap[hh];
               const int64_t slot = ray * a.K + (mp >> 16);
               *reinterpret_cast<float2*>(a.gT + 2 * slot) =
                   make_float2(hp[3], g_eta * rc.eta * (1.0f - rc.eta));
