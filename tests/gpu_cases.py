@@ -35,7 +35,8 @@ BF16 path: compared with the oracle's BF16-rounding mode; hidden activations
 may round differently where FP32 and FP64 accumulations straddle a bfloat16
 rounding boundary (one bfloat16 ulp = 2^-8 relative), so rendered outputs are
 checked at max|err| <= 2^-6 max|ref| + 1e-4 S, and the error against the FP64
-oracle is reported as PSNR.  The decoder alone is checked per entry
+oracle is reported as PSNR; single-decoder renders are also checked per ray
+(bf16_render_bound).  The decoder alone is checked per entry
 (bf16_decoder_bound): each output within the error that FP32 accumulation
 can produce, carried through the layers, where a hidden activation may take
 the neighbouring bfloat16 value only if its exact pre-activation lies within
@@ -75,7 +76,7 @@ C_W = 8.0          # single decoder: the midpoint's cell coordinates to a few ul
 C_W_LF = 64.0      # light field: the surface point moves with eta's error
 
 
-def bf16_decoder_bound(params, widths, X):
+def bf16_decoder_bound(params, widths, X, dX=None):
     """(ref, bound): the oracle's BF16-mode decoder outputs (n, out) and, per
     entry, the largest |out - ref| of an implementation that rounds X, the
     weights and every hidden activation to bfloat16 exactly as the oracle
@@ -86,11 +87,14 @@ def bf16_decoder_bound(params, widths, X):
     |W| times the error its inputs already carry.  ReLU and the rounding are
     monotone, so a pre-activation known to within dz rounds to a value within
     max(r(h(z + dz)) - r(h(z)), r(h(z)) - r(h(z - dz))) of the oracle's: zero
-    unless a rounding boundary lies within dz of z."""
+    unless a rounding boundary lies within dz of z.  ``dX`` bounds an error
+    of X itself before its rounding (the same rule gives the rounded input's
+    error)."""
     from oracle.render import bf16_round as r
     layers = split_params(params, widths)
-    a = r(np.asarray(X, np.float64))
-    e = np.zeros_like(a)
+    X = np.asarray(X, np.float64)
+    a = r(X)
+    e = np.zeros_like(a) if dX is None else np.maximum(r(X + dX) - a, a - r(X - dX))
     for li, (W, b) in enumerate(layers):
         Wr = r(W)
         absW = np.abs(Wr)
@@ -104,6 +108,87 @@ def bf16_decoder_bound(params, widths, X):
         a = h(z)
         e = np.maximum(h(z + dz) - a, a - h(z - dz))
     raise ValueError("empty MLP")
+
+
+def bf16_render_bound(st, F, dX_ulps=16.0):
+    """Per ray, bounds on |rgb - rgb_ref| (n, 3), |depth - depth_ref| and
+    |acc - acc_ref| (n,) for a device render in the BF16 mode against the
+    oracle's BF16-mode render state ``st`` (single decoder, no view
+    direction).  The device interpolates the bfloat16 feature rows in FP32
+    (cell coordinates and weights a few ulps off: dX = dX_ulps 2^-24
+    sum_j (w_j + D_j) |F_j|, D_j = weight_sensitivity; F unrounded, its rows
+    are rounded here), rounds X to bfloat16,
+    runs the decoder with FP32 sums (bf16_decoder_bound) and evaluates
+    sigmoid, tau, exp and Eq. 3 in FP32.  Each step's error is carried in
+    absolute terms: |dc| <= |do|/4 + 4 ulps, |dtau| <= dtau |do_3| + 2 ulps,
+    |d exp(-tau)| <= exp(-tau + |dtau|) |dtau| + 4 ulps (so for alpha),
+    then along the ray T_{i+1} = T_i e_i, w_i = T_i alpha_i and the three
+    sums, each product and sum adding one rounding."""
+    from oracle.render import bf16_round, weight_sensitivity
+    assert st.X.shape[1] == st.widths[0], "view-direction input not covered"
+    D = weight_sensitivity(st.u)
+    absF = np.abs(bf16_round(np.asarray(F[st.corners], np.float64)))      # the rows the hits read
+    dX = dX_ulps * EPS32 * np.einsum("mj,mjc->mc", st.wj + D, absF)
+    o, do = bf16_decoder_bound(st.params, st.widths, st.X, dX)
+    c = 1.0 / (1.0 + np.exp(-o[:, :3]))
+    dc = 0.25 * do[:, :3] + 4 * EPS32
+    sig = np.maximum(o[:, 3], 0.0)
+    tau = sig * st.dtau
+    dtau = do[:, 3] * st.dtau + 2 * EPS32 * tau
+    e = np.exp(-tau)
+    de = np.exp(-tau + dtau) * dtau + 4 * EPS32 * e
+    alpha = 1.0 - e
+    dalpha = de + 4 * EPS32 * alpha
+    n, K = st.n, st.K
+    dense = lambda v, fill=0.0: _dense(v, st, fill)
+    C_, DC = dense(c), dense(dc)
+    E, DE, A, DA = dense(e, 1.0), dense(de), dense(alpha), dense(dalpha)
+    TM = dense(st.tmid[st.ray_i, st.slot_i])
+    T = np.ones(n)
+    dT = np.zeros(n)
+    rgb, drgb = np.zeros((n, 3)), np.zeros((n, 3))
+    dep, ddep = np.zeros(n), np.zeros(n)
+    acc, dacc = np.zeros(n), np.zeros(n)
+    for k in range(K):
+        w = T * A[:, k]
+        dw = dT * A[:, k] + T * DA[:, k] + EPS32 * w
+        rgb += w[:, None] * C_[:, k]
+        drgb += dw[:, None] * C_[:, k] + w[:, None] * DC[:, k] + EPS32 * np.abs(rgb)
+        dep += w * TM[:, k]
+        ddep += dw * np.abs(TM[:, k]) + w * EPS32 * np.abs(TM[:, k]) + EPS32 * np.abs(dep)
+        acc += w
+        dacc += dw + EPS32 * acc
+        Tn = T * E[:, k]
+        dT = dT * E[:, k] + T * DE[:, k] + EPS32 * Tn
+        T = Tn
+    return drgb, ddep, dacc
+
+
+def assert_bf16_render_close(rgb, dep, acc, ref, st, F, name=""):
+    """Every ray's BF16 render outputs within bf16_render_bound of the
+    oracle's BF16-mode render ``ref`` = (rgb, depth, acc) with state st."""
+    drgb, ddep, dacc = bf16_render_bound(st, F)
+    worst = 0.0
+    for got, exp, b, what in ((rgb, ref[0], drgb, "rgb"), (dep, ref[1], ddep, "depth"),
+                              (acc, ref[2], dacc, "acc")):
+        if got is None:
+            continue
+        err = np.abs(np.asarray(got, np.float64) - exp)
+        bad = err > b
+        with np.errstate(divide="ignore", invalid="ignore"):
+            worst = max(worst, float(np.max(np.where(b > 0, err / b, np.where(err > 0, np.inf, 0.0)),
+                                            initial=0.0)))
+        assert not bad.any(), (f"{name} {what}: {bad.sum()} of {bad.size} outside the per-ray bound, "
+                               f"worst err {err[bad].max():.3g} vs bound {b[bad][np.argmax(err[bad])]:.3g}")
+    print(f"{name}: BF16 render max err / bound = {worst:.3g}")
+
+
+def _dense(v, st, fill):
+    """Per-hit values (m, ...) into the dense per-ray layout (n, K, ...)."""
+    v = np.asarray(v, np.float64)
+    out = np.full((st.n, st.K) + v.shape[1:], fill)
+    out[st.ray_i, st.slot_i] = v
+    return out
 
 
 def grad_error_ratio(got, exp, mag, unit=EPS32, wmag=None, c_w=C_W):

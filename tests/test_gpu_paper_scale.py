@@ -12,7 +12,8 @@ from oracle.render import (loss as oracle_loss, render as oracle_render, render_
                            render_backward_weight_scale)
 from oracle.trace import trace_hits as oracle_trace
 from synth.configs import get_config
-from tests.gpu_cases import (BF16_ULP, C_PARAM, C_W, C_W_LF, EPS32, assert_grad_close, assert_outputs_close,
+from tests.gpu_cases import (BF16_ULP, C_PARAM, C_W, C_W_LF, EPS32, assert_bf16_render_close, assert_grad_close,
+                             assert_outputs_close,
                              cosine, decoder_kinks as _decoder_kinks, lf_kinks as _lf_kinks, loss_scales,
                              residual_terms,
                              psnr)
@@ -75,10 +76,10 @@ def test_render_full_view_sampled(gpu_lib, paper, precision):
         assert_outputs_close(dep[idx], ed, max(1.0, np.abs(ed).max()), "depth")
         assert_outputs_close(acc[idx], ea, 1.0, "acc")
     else:
-        br, bd, ba, _ = oracle_render(paper["oc"], paper["F"], paper["p"], w.widths, o[idx], d[idx], hits,
-                                      bf16=True)
+        br, bd, ba, bst = oracle_render(paper["oc"], paper["F"], paper["p"], w.widths, o[idx], d[idx], hits,
+                                        bf16=True)
         er, _, _, _ = oracle_render(paper["oc"], paper["F"], paper["p"], w.widths, o[idx], d[idx], hits)
-        assert np.abs(rgb[idx] - br).max() <= 2 ** -6 * np.abs(br).max() + 1e-4
+        assert_bf16_render_close(rgb[idx], dep[idx], acc[idx], (br, bd, ba), bst, paper["F"], "paper-scale bf16")
         assert psnr(rgb[idx], er) > 40.0
 
 

@@ -8,7 +8,8 @@ from oracle.render import (bf16_round, loss as oracle_loss, mlp_forward as oracl
                            render_backward_hit_magnitude,
                            render_backward_weight_scale)
 from synth.configs import get_config, scene_from_leaves, tiny_workload, xavier_params
-from tests.gpu_cases import (C_PARAM, C_W_LF, Case, assert_grad_close, assert_outputs_close, bf16_decoder_bound, psnr,
+from tests.gpu_cases import (C_PARAM, C_W_LF, Case, assert_bf16_render_close, assert_grad_close, assert_outputs_close,
+                             bf16_decoder_bound, psnr,
                              loss_scales, residual_terms)
 from tests.helpers import random_rays
 
@@ -92,12 +93,9 @@ def test_render_bf16_against_bf16_oracle(gpu_lib):
     for name, case in _scene_cases(gpu_lib):
         o, d = random_rays(np.random.default_rng(1), 2000)
         rgb, dep, acc = case.gpu_render(o, d, "bf16")
-        br, bd, ba, _ = case.oracle(o, d, bf16=True)
+        br, bd, ba, bst = case.oracle(o, d, bf16=True)
         er, ed, ea, _ = case.oracle(o, d)
-        S = max(1.0, np.abs(ed).max())
-        assert np.abs(rgb - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4, name
-        assert np.abs(dep - bd).max() <= 2 ** -6 * S + 1e-4 * S, name
-        assert np.abs(acc - ba).max() <= 2 ** -6 + 1e-4, name
+        assert_bf16_render_close(rgb, dep, acc, (br, bd, ba), bst, case.F, name)
         assert psnr(rgb, er) > 35.0, (name, psnr(rgb, er))
 
 
@@ -541,11 +539,9 @@ def test_full_items_of_max_hits(gpu_lib):
     assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
     assert_outputs_close(rgb, er, 1.0, "full items rgb")
     assert_outputs_close(dep, ed, max(1.0, np.abs(ed).max()), "full items depth")
-    br, bd, _, _ = case.oracle(o, d, bf16=True)
+    br, bd, ba, bst = case.oracle(o, d, bf16=True)
     rgb16, dep16, _ = _train_outputs(case, o, d, t_rgb, t_dep, "bf16")
-    S = max(1.0, np.abs(bd).max())
-    assert np.abs(rgb16 - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4
-    assert np.abs(dep16 - bd).max() <= 2 ** -6 * S + 1e-4 * S
+    assert_bf16_render_close(rgb16, dep16, None, (br, bd, ba), bst, case.F, "full items bf16")
     keep = case.smooth_rays(o, d)
     assert keep.size > n // 3
     g_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)

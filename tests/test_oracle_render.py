@@ -615,3 +615,81 @@ def test_bf16_decoder_bound_holds_for_fp32_sums_and_catches_rounding_mistakes(wi
     for kw in ({"hidden": _bf16_truncate}, {"hidden": lambda v: v}, {"round_weights": False}):
         out = _decoder_fp32_accumulation(p, widths, X, **kw)
         assert np.mean(np.abs(out - ref) > bound) > 0.5, kw
+
+
+def _render_fp32_emulation(st, F, mistake=None):
+    """The BF16 render as a device computes it, emulated in float32 on the
+    oracle's hits: FP32 cell weights and interpolation of the bfloat16 rows,
+    the decoder with FP32 sums (bfloat16 operands), FP32 sigmoid / exp and
+    Eq. 3 with a running transmittance.  ``mistake`` plants one error."""
+    f32 = np.float32
+    Fb = f32(bf16_round(np.asarray(F, np.float64)))
+    u = f32(st.u)
+    one = f32(1.0)
+    wx = [one - u[:, 0], u[:, 0]]
+    wy = [one - u[:, 1], u[:, 1]]
+    wz = [one - u[:, 2], u[:, 2]]
+    X = np.zeros((u.shape[0], Fb.shape[1]), f32)
+    for j in range(8):
+        wj = (wx[j & 1] * wy[(j >> 1) & 1]) * wz[j >> 2]
+        X = X + wj[:, None] * Fb[st.corners[:, j]]
+    if mistake == "unrounded input":
+        o = _decoder_no_input_rounding(st.params, st.widths, X.astype(np.float64))
+    elif mistake == "truncated hidden":
+        o = _decoder_fp32_accumulation(st.params, st.widths, X.astype(np.float64), hidden=_bf16_truncate)
+    else:
+        o = _decoder_fp32_accumulation(st.params, st.widths, X.astype(np.float64))
+    o = f32(o)
+    c = one / (one + np.exp(-o[:, :3]))
+    tau = np.maximum(o[:, 3], f32(0.0)) * f32(st.dtau)
+    e = np.exp(-tau)
+    alpha = -np.expm1(-tau)
+    n, K = st.n, st.K
+    rgb = np.zeros((n, 3), f32)
+    dep = np.zeros(n, f32)
+    acc = np.zeros(n, f32)
+    T = np.ones(n, f32)
+    tm = f32(st.tmid)
+    for k in range(K):
+        sel = st.slot_i == k
+        ri = st.ray_i[sel]
+        w = T[ri] * (e[sel] if mistake == "alpha from transmittance" else alpha[sel])
+        rgb[ri] += w[:, None] * c[sel]
+        dep[ri] += w * tm[ri, k]
+        acc[ri] += w
+        T[ri] = T[ri] * e[sel]
+    return rgb.astype(np.float64), dep.astype(np.float64), acc.astype(np.float64)
+
+
+def _decoder_no_input_rounding(p, widths, X):
+    a = np.float32(X)
+    layers = split_params(p, widths)
+    for li, (W, b) in enumerate(layers):
+        z = a @ np.float32(bf16_round(W)).T + np.float32(b)
+        if li == len(layers) - 1:
+            return z.astype(np.float64)
+        a = np.float32(bf16_round(np.maximum(z.astype(np.float64), 0.0)))
+
+
+def test_bf16_render_bound_holds_for_fp32_emulation_and_catches_mistakes():
+    """The per-ray bound of the BF16 render parity test: met by a float32
+    emulation of the device's arithmetic on several scenes, broken by an
+    input left unrounded, by truncated hidden activations and by a wrong
+    opacity in Eq. 3."""
+    from tests.gpu_cases import bf16_render_bound
+    for seed in (12, 13, 14):
+        oc, F, p, widths, o, d, hits, _, _ = _fd_setup(seed)
+        p = p.copy()
+        p[-1] = 1.5
+        rgb, dep, acc, st = render(oc, F, p, widths, o, d, hits, bf16=True)
+        drgb, ddep, dacc = bf16_render_bound(st, F)
+        assert np.median(drgb[acc > 0]) < 1e-3
+        er, ed, ea = _render_fp32_emulation(st, F)
+        assert np.all(np.abs(er - rgb) <= drgb), seed
+        assert np.all(np.abs(ed - dep) <= ddep), seed
+        assert np.all(np.abs(ea - acc) <= dacc), seed
+        hit = acc > 0
+        for m in ("unrounded input", "truncated hidden", "alpha from transmittance"):
+            mr, md, ma = _render_fp32_emulation(st, F, mistake=m)
+            bad = np.any(np.abs(mr - rgb) > drgb, axis=1) | (np.abs(ma - acc) > dacc)
+            assert np.mean(bad[hit]) > 0.3, (seed, m, np.mean(bad[hit]))
