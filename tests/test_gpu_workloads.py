@@ -23,7 +23,8 @@ from oracle.render import (loss as oracle_loss, render as oracle_render, render_
                            render_backward_weight_scale)
 from oracle.trace import trace_hits as oracle_trace
 from synth.configs import get_config, get_multi
-from tests.gpu_cases import (C_PARAM, assert_grad_close, assert_outputs_close, decoder_kinks, psnr,
+from tests.gpu_cases import (C_PARAM, assert_bf16_render_close, assert_grad_close, assert_outputs_close,
+                             decoder_kinks, psnr,
                              loss_scales, residual_terms)
 
 pytestmark = pytest.mark.gpu
@@ -214,8 +215,9 @@ def test_multi_scene_full_size_one_launch(gpu_lib, multi):
         assert_outputs_close(r32, er, 1.0, f"scene {i} rgb")
         assert_outputs_close(d32, ed, max(1.0, np.abs(ed).max()), f"scene {i} depth")
         assert_outputs_close(a32, ea, 1.0, f"scene {i} acc")
-        br, _, _, _ = oracle_render(oc, F64, mu["p"], m.widths, o, d, hits, bf16=True)
-        assert np.abs(outs["bf16"][0][idx] - br).max() <= 2 ** -6 * max(np.abs(br).max(), 1e-3) + 1e-4
+        br, bd, ba, bst = oracle_render(oc, F64, mu["p"], m.widths, o, d, hits, bf16=True)
+        r16, d16, a16 = (x[idx] for x in outs["bf16"])
+        assert_bf16_render_close(r16, d16, a16, (br, bd, ba), bst, F64, f"scene {i} bf16")
         hit_rays += int(np.count_nonzero(hits[3]))
         # upstream gradients on the kink-free sampled rays
         bad = np.zeros(idx.size, bool)
