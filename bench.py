@@ -150,8 +150,8 @@ def main():
     if args.cpu_child:
         return cpu_child(args.cpu_child)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
-                 "(the sharding design is described in DESIGN.md); run with --gpus 1")
+        sys.exit("bench.py measures one GPU only: the library has no multi-GPU path; "
+                 "run with --gpus 1")
     import torch
 
     from paper_2205_07058_amd import svlf
