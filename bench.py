@@ -155,13 +155,13 @@ def main():
     import torch
 
     from paper_2205_07058_amd import svlf
-    from synth.configs import get_config
+    from synth.configs import get_workload
 
     sections = set(args.sections.split(",")) if args.sections != "all" else set(ALL_SECTIONS)
     torch.cuda.set_device(0)
     svlf.load()
     t0 = time.time()
-    w = get_config(3)
+    w = get_workload("surfaces_d9")
     sc = w.scene()
     log(f"scene: depth {sc.depth}, {sc.leaf_ijk.shape[0]} leaves ({100 * sc.fraction:.2f}%), "
         f"{sc.n_vertices} vertices ({time.time() - t0:.1f}s)")
@@ -458,12 +458,12 @@ def bench_small(torch, svlf, timer, args):
     scene (800x800, K = 8, decoder 16-64-64-64-4), and the training pass on
     the depth-7 scene with a 2^18-ray batch from 50 views (FP32, the
     workload's precision, and BF16)."""
-    from synth.configs import get_config
+    from synth.configs import get_workload
     T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
     out = {}
     ws = svlf.Workspace()
-    for i in (0, 1):
-        w = get_config(i)
+    for name in ("shell_d4", "ellipsoids_d7"):
+        w = get_workload(name)
         sc = w.scene()
         scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features(), bf16=True)
         params = T(w.params())
@@ -480,10 +480,10 @@ def bench_small(torch, svlf, timer, args):
                                                   workspace=ws), args.steps, args.warmup)
             r[f"fwd_{prec}_ms"] = round(ms / args.steps, 4)
             r[f"fwd_{prec}_rays_per_s"] = round(n / (ms / args.steps * 1e-3), 1)
-        log(f"workload {i} forward: fp32 {r['fwd_fp32_rays_per_s'] / 1e6:.1f} M rays/s, "
+        log(f"{name} forward: fp32 {r['fwd_fp32_rays_per_s'] / 1e6:.1f} M rays/s, "
             f"bf16 {r['fwd_bf16_rays_per_s'] / 1e6:.1f} M rays/s ({n} rays)")
-        out[f"cfg{i}"] = r
-    w = get_config(2)
+        out[name] = r
+    w = get_workload("ellipsoids_d7_train")
     sc = w.scene()
     scene = svlf.DeviceScene.from_host(sc.leaf_ijk, sc.depth, w.features(), bf16=True)
     params = T(w.params())
@@ -501,9 +501,9 @@ def bench_small(torch, svlf, timer, args):
                           args.steps, args.warmup)
         r[f"train_{prec}_ms"] = round(ms / args.steps, 4)
         r[f"train_{prec}_rays_per_s"] = round(n / (ms / args.steps * 1e-3), 1)
-    log(f"workload 2 train step: fp32 {r['train_fp32_rays_per_s'] / 1e6:.1f} M rays/s, "
+    log(f"ellipsoids_d7_train step: fp32 {r['train_fp32_rays_per_s'] / 1e6:.1f} M rays/s, "
         f"bf16 {r['train_bf16_rays_per_s'] / 1e6:.1f} M rays/s")
-    out["cfg2"] = r
+    out["ellipsoids_d7_train"] = r
     return out
 
 
@@ -636,7 +636,7 @@ def cpu_child(path):
     """Child-process half of cpu_baseline: prints one JSON line."""
     import multiprocessing as mp
     from oracle.octree import Octree
-    from synth.configs import get_config
+    from synth.configs import get_workload
     z = np.load(path)
     o, d, rgb_t, dep_t = z["o"], z["d"], z["rgb_t"], z["dep_t"]
     n = o.shape[0]
@@ -646,22 +646,22 @@ def cpu_child(path):
         usable = os.cpu_count() or 1
     P = max(1, min(usable, 16))
     t0 = time.time()
-    w = get_config(3)
+    w = get_workload("surfaces_d9")
     sc = w.scene()
     F = w.features().astype(np.float64)
     _G["train"] = dict(o=o, d=d, rgb_t=rgb_t, dep_t=dep_t, oc=Octree(sc.leaf_ijk, sc.depth), F=F, p=w.params(),
                        widths=w.widths, K=w.K)
     fw = {}
-    for i in (0, 1):
-        wi = get_config(i)
+    for name in ("shell_d4", "ellipsoids_d7"):
+        wi = get_workload(name)
         sci = wi.scene()
         oi, di = wi.view_rays(0)
-        _G[f"fwd{i}"] = dict(o=oi, d=di, oc=Octree(sci.leaf_ijk, sci.depth), F=wi.features(), p=wi.params(),
-                             widths=wi.widths, K=wi.K)
-        fw[i] = oi.shape[0]
+        _G[f"fwd_{name}"] = dict(o=oi, d=di, oc=Octree(sci.leaf_ijk, sci.depth), F=wi.features(),
+                                 p=wi.params(), widths=wi.widths, K=wi.K)
+        fw[name] = oi.shape[0]
     ov, dv = w.view_rays(0)
     sel = np.sort(np.random.default_rng(3).choice(ov.shape[0], 1 << 14, replace=False))
-    _G["fwd3"] = dict(_G["train"], o=ov[sel], d=dv[sel])
+    _G["fwd_surfaces_d9"] = dict(_G["train"], o=ov[sel], d=dv[sel])
     log(f"oracle set-up ({time.time() - t0:.1f}s); {P} worker processes ({usable} usable cores)")
 
     def chunks(kind, m, k):
@@ -674,7 +674,7 @@ def cpu_child(path):
     single = 8192 / (time.time() - t1)
     res = {}
     with mp.get_context("fork").Pool(P) as pool:
-        pool.map(_oracle_chunk, chunks("fwd0", fw[0], P))          # warm the workers
+        pool.map(_oracle_chunk, chunks("fwd_shell_d4", fw["shell_d4"], P))          # warm the workers
         t2 = time.time()
         parts = pool.map(_oracle_chunk, chunks("train", n, P))
         gF = np.zeros_like(F)
@@ -683,21 +683,22 @@ def cpu_child(path):
             gF[rows] += g
             gp = gp + gpp
         res["train"] = n / (time.time() - t2)
-        for kind, m in (("fwd0", fw[0]), ("fwd1", fw[1]), ("fwd3", 1 << 14)):
+        for kind, m in (("fwd_shell_d4", fw["shell_d4"]), ("fwd_ellipsoids_d7", fw["ellipsoids_d7"]),
+                        ("fwd_surfaces_d9", 1 << 14)):
             t3 = time.time()
             pool.map(_oracle_chunk, chunks(kind, m, P))
             res[kind] = m / (time.time() - t3)
     log(f"oracle train pass on {n} rays with {P} processes: {res['train']:.0f} rays/s "
-        f"(one process: {single:.0f} rays/s); forward: depth-4 view {res['fwd0']:.0f}, depth-7 view "
-        f"{res['fwd1']:.0f}, paper-scale view sample {res['fwd3']:.0f} rays/s")
+        f"(one process: {single:.0f} rays/s); forward: depth-4 view {res['fwd_shell_d4']:.0f}, depth-7 view "
+        f"{res['fwd_ellipsoids_d7']:.0f}, paper-scale view sample {res['fwd_surfaces_d9']:.0f} rays/s")
     out = {"value": round(res["train"], 2), "unit": "rays/s", "cores": P, "kind": "oracle",
            "sample": f"{n} seeded rays of the 2^20-ray batch: FP64 oracle trace + render + loss + backward "
                      f"(feature gradients reduced over the chunks), {P} worker processes with one BLAS "
                      f"thread each; octree build excluded",
            "single_process_rays_per_s": round(single, 2),
-           "forward_rays_per_s": {"depth4_view_64x64": round(res["fwd0"], 1),
-                                  "depth7_view_800x800": round(res["fwd1"], 1),
-                                  "paper_scale_view_sample_2^14": round(res["fwd3"], 1)},
+           "forward_rays_per_s": {"depth4_view_64x64": round(res["fwd_shell_d4"], 1),
+                                  "depth7_view_800x800": round(res["fwd_ellipsoids_d7"], 1),
+                                  "paper_scale_view_sample_2^14": round(res["fwd_surfaces_d9"], 1)},
            "nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": _cpu_info()}
     print(json.dumps(out), flush=True)
 

@@ -12,4 +12,4 @@ Random draws use ``numpy.random.Generator(PCG64)`` streams derived from one
 scene -> features -> MLP -> cameras -> batch (see ``configs.streams``).
 """
 
-from .configs import CONFIGS, Workload, get_config, streams  # noqa: F401
+from .configs import WORKLOADS, Workload, get_workload, streams  # noqa: F401

@@ -1,18 +1,20 @@
-"""The five synthetic workloads (shapes follow the RTMV/SVLF setup).
+"""The synthetic workloads (shapes follow the RTMV/SVLF setup).
 
-==== ============================================================ ==========
-name scene                                                        rays
-==== ============================================================ ==========
-0    depth 4, shell 0.6 +- 0.05, C=8, MLP 8-32-32-4, K=4            64x64 view
-1    depth 7, 12 solid rotated ellipsoids (~3%), C=16,              800x800 view
-     MLP 16-64-64-64-4, K=8
-2    workload-1 scene, 50 training + 5 held-out views, analytic     2^18 batch
-     Lambertian targets
-3    depth 9, 40 rotated ellipsoids + 20 boxes, surface cells       1600^2 view,
-     scaled to ~1%, C=32, MLP 32-64-64-64-4, K=8                    2^20 batch
-4    8 scenes, depths {7,8,8,9,9,10,10,10}, 0.5-3%, C=32,           2^16..2^20
-     MLP 32-64-64-64-4, K=8                                         per scene
-==== ============================================================ ==========
+=================== ================================================ ==========
+name                scene                                            rays
+=================== ================================================ ==========
+shell_d4            depth 4, shell 0.6 +- 0.05, C=8, MLP 8-32-32-4,  64x64 view
+                    K=4
+ellipsoids_d7       depth 7, 12 solid rotated ellipsoids (~3%),      800x800
+                    C=16, MLP 16-64-64-64-4, K=8                     view
+ellipsoids_d7_train the ellipsoids_d7 scene, 50 training + 5         2^18 batch
+                    held-out views, analytic Lambertian targets
+surfaces_d9         depth 9, 40 rotated ellipsoids + 20 boxes,       1600^2 view,
+                    surface cells scaled to ~1%, C=32,               2^20 batch
+                    MLP 32-64-64-64-4, K=8
+(get_multi)         8 scenes, depths {7,8,8,9,9,10,10,10}, 0.5-3%,   2^16..2^20
+                    C=32, MLP 32-64-64-64-4, K=8                     per scene
+=================== ================================================ ==========
 
 Features are N(0, 0.1^2) per vertex; MLP weights are Xavier-uniform with zero
 biases, laid out per layer as W[out][in] (row-major) followed by b[out], all
@@ -231,35 +233,35 @@ def _scene_paper_scale(w):
 
 
 _SCENE_BUILDERS = {
-    "cfg0": _scene_shell,
-    "cfg1": _scene_ellipsoids12,
-    "cfg2": _scene_ellipsoids12,
-    "cfg3": _scene_paper_scale,
+    "shell_d4": _scene_shell,
+    "ellipsoids_d7": _scene_ellipsoids12,
+    "ellipsoids_d7_train": _scene_ellipsoids12,
+    "surfaces_d9": _scene_paper_scale,
 }
 
 
-def _make(i, seed=None):
-    if i == 0:
-        return Workload("cfg0", 0 if seed is None else seed, 4, 8, (8, 32, 32, 4), 4, 64, 3.0,
+def _make(name, seed=None):
+    if name == "shell_d4":
+        return Workload("shell_d4", 0 if seed is None else seed, 4, 8, (8, 32, 32, 4), 4, 64, 3.0,
                         description="forward FP32, depth 4 shell, 64x64, K=4")
-    if i == 1:
-        return Workload("cfg1", 1 if seed is None else seed, 7, 16, (16, 64, 64, 64, 4), 8, 800, 4.0,
-                        description="forward FP32, depth 7, 12 ellipsoids, 800x800, K=8")
-    if i == 2:
-        # same scene as cfg1 (same seed drives the scene stream)
-        return Workload("cfg2", 1 if seed is None else seed, 7, 16, (16, 64, 64, 64, 4), 8, 800, 4.0,
-                        n_views=50, n_heldout=5, batch=1 << 18,
-                        description="train step FP32 on the cfg1 scene, batch 2^18 from 50 views")
-    if i == 3:
-        return Workload("cfg3", 3 if seed is None else seed, 9, 32, (32, 64, 64, 64, 4), 8, 1600, 4.0,
+    if name == "ellipsoids_d7":
+        return Workload("ellipsoids_d7", 1 if seed is None else seed, 7, 16, (16, 64, 64, 64, 4), 8, 800,
+                        4.0, description="forward FP32, depth 7, 12 ellipsoids, 800x800, K=8")
+    if name == "ellipsoids_d7_train":
+        # same scene as ellipsoids_d7 (same seed drives the scene stream)
+        return Workload("ellipsoids_d7_train", 1 if seed is None else seed, 7, 16, (16, 64, 64, 64, 4), 8,
+                        800, 4.0, n_views=50, n_heldout=5, batch=1 << 18,
+                        description="train step FP32 on the depth-7 ellipsoid scene, batch 2^18 from 50 views")
+    if name == "surfaces_d9":
+        return Workload("surfaces_d9", 3 if seed is None else seed, 9, 32, (32, 64, 64, 64, 4), 8, 1600, 4.0,
                         n_views=50, n_heldout=5, batch=1 << 20,
                         description="depth 9, 40 ellipsoids + 20 boxes (~1%), 1600^2, batch 2^20")
-    raise KeyError(i)
+    raise KeyError(name)
 
 
-CONFIGS = (0, 1, 2, 3, 4)
+WORKLOADS = ("shell_d4", "ellipsoids_d7", "ellipsoids_d7_train", "surfaces_d9")
 
-# Workload 4: ragged batch of scenes sharing one decoder (C = 32, MLP
+# The multi-scene workload: ragged batch of scenes sharing one decoder (C = 32, MLP
 # 32-64-64-64-4, K = 8).  Depths as specified; occupied fractions are fixed
 # points of the stated 0.5-3% range (largest at the coarsest depth, so no
 # scene exceeds ~6M leaves); ray counts are seeded log-uniform in
@@ -321,8 +323,9 @@ def get_multi(seed=4, small=False) -> MultiScene:
     return MultiScene(seed, MULTI_DEPTHS, MULTI_FRACTIONS)
 
 
-def get_config(i, seed=None) -> Workload:
-    return _make(i, seed)
+def get_workload(name, seed=None) -> Workload:
+    """One of the named workloads (WORKLOADS)."""
+    return _make(name, seed)
 
 
 def tiny_workload(seed, depth, C, widths, K, image=16, kind="ellipsoids", n_obj=3,

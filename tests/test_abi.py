@@ -11,7 +11,7 @@ import pytest
 
 from oracle.octree import Octree
 from paper_2205_07058_amd import svlf
-from synth.configs import get_config, tiny_workload
+from synth.configs import get_workload, tiny_workload
 from tests.helpers import crafted_occupancy
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "svlf.h")
@@ -176,10 +176,10 @@ def _expected_nodes(oc: Octree):
     return np.concatenate(rows, axis=0), offs
 
 
-@pytest.mark.parametrize("case", ["cfg0", "tiny_d3", "checker_d4", "single_d5", "full_d2", "random_d6"])
+@pytest.mark.parametrize("case", ["shell_d4", "tiny_d3", "checker_d4", "single_d5", "full_d2", "random_d6"])
 def test_host_octree_matches_oracle(case):
-    if case == "cfg0":
-        sc = get_config(0).scene()
+    if case == "shell_d4":
+        sc = get_workload("shell_d4").scene()
         ijk, depth = sc.leaf_ijk, sc.depth
     elif case == "tiny_d3":
         sc = tiny_workload(4, 3, 8, (8, 32, 32, 4), 4).scene()

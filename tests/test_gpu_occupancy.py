@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle.octree import occupancy_from_depth
-from synth.configs import get_config, tiny_workload
+from synth.configs import get_workload, tiny_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -66,7 +66,7 @@ def test_occupancy_from_rendered_depth_maps(gpu_lib):
 
 def test_occupancy_paper_scale_view(gpu_lib):
     """One 1600^2 view of the paper-scale scene at level 9."""
-    w = get_config(3)
+    w = get_workload("surfaces_d9")
     o, d = w.view_rays(0)
     _, t = w.targets(o, d)
     got = _gpu(gpu_lib, o, d, t, 9)

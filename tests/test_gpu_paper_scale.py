@@ -11,7 +11,7 @@ from oracle.render import (loss as oracle_loss, render as oracle_render, render_
                            render_backward_hit_magnitude,
                            render_backward_weight_scale)
 from oracle.trace import trace_hits as oracle_trace
-from synth.configs import get_config
+from synth.configs import get_workload
 from tests.gpu_cases import (BF16_ULP, C_PARAM, C_W, C_W_LF, EPS32, assert_bf16_render_close, assert_grad_close,
                              assert_outputs_close,
                              cosine, decoder_kinks as _decoder_kinks, lf_kinks as _lf_kinks, loss_scales,
@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def paper(gpu_lib):
     import torch
-    w = get_config(3)
+    w = get_workload("surfaces_d9")
     sc = w.scene()
     F = w.features()
     p = w.params().copy()
@@ -387,7 +387,7 @@ def _gpu_train(gpu_lib, scene, params, opts, o, d, rgb_t, dep_t, lf=False):
 
 
 def paper_widths():
-    return tuple(get_config(3).widths)
+    return tuple(get_workload("surfaces_d9").widths)
 
 
 def _check_bf16_grads(got, exp, mag, name, wmag=None, c_w=C_W):

@@ -7,7 +7,7 @@ import pytest
 from oracle.render import (bf16_round, loss as oracle_loss, mlp_forward as oracle_mlp, render_backward,
                            render_backward_hit_magnitude,
                            render_backward_weight_scale)
-from synth.configs import get_config, scene_from_leaves, tiny_workload, xavier_params
+from synth.configs import get_workload, scene_from_leaves, tiny_workload, xavier_params
 from tests.gpu_cases import (C_PARAM, C_W_LF, Case, assert_bf16_render_close, assert_grad_close, assert_outputs_close,
                              bf16_decoder_bound, psnr,
                              loss_scales, residual_terms)
@@ -56,7 +56,7 @@ def test_decoder_bf16(gpu_lib, widths, n):
 
 
 def _scene_cases(svlf):
-    yield "cfg0", Case.from_workload(svlf, get_config(0), feat_scale=4.0, sigma_bias=0.8)
+    yield "shell_d4", Case.from_workload(svlf, get_workload("shell_d4"), feat_scale=4.0, sigma_bias=0.8)
     w = tiny_workload(7, 5, 16, (16, 64, 64, 64, 4), 8, n_obj=3)
     yield "tiny16", Case.from_workload(svlf, w, feat_scale=5.0, sigma_bias=1.0)
     w = tiny_workload(8, 6, 32, (32, 64, 64, 64, 4), 8, n_obj=4)
@@ -102,14 +102,14 @@ def test_render_bf16_against_bf16_oracle(gpu_lib):
 def test_workload1_full_view_sampled(gpu_lib):
     """Full 800x800 view rendered in one call (the launch a bench would
     time); 4096 seeded rays compared with the oracle."""
-    case = Case.from_workload(gpu_lib, get_config(1), feat_scale=3.0, sigma_bias=0.5)
-    o, d = get_config(1).view_rays()
+    case = Case.from_workload(gpu_lib, get_workload("ellipsoids_d7"), feat_scale=3.0, sigma_bias=0.5)
+    o, d = get_workload("ellipsoids_d7").view_rays()
     rgb, dep, acc = case.gpu_render(o, d)
     idx = np.random.default_rng(7).choice(o.shape[0], 4096, replace=False)
     er, ed, ea, st = case.oracle(o[idx], d[idx])
-    assert_outputs_close(rgb[idx], er, 1.0, "cfg1 rgb")
-    assert_outputs_close(dep[idx], ed, max(1.0, np.abs(ed).max()), "cfg1 depth")
-    assert_outputs_close(acc[idx], ea, 1.0, "cfg1 acc")
+    assert_outputs_close(rgb[idx], er, 1.0, "ellipsoids_d7 rgb")
+    assert_outputs_close(dep[idx], ed, max(1.0, np.abs(ed).max()), "ellipsoids_d7 depth")
+    assert_outputs_close(acc[idx], ea, 1.0, "ellipsoids_d7 acc")
     assert np.all(acc >= 0) and np.all(acc <= 1 + 1e-6) and np.all(rgb <= acc[:, None] + 1e-6)
 
 
@@ -234,7 +234,7 @@ def test_multi_scene_render_and_backward(gpu_lib):
         w = tiny_workload(seed, depth, 16, (16, 64, 64, 64, 4), 8, n_obj=2)
         sc = w.scene()
         F = w.features() * 4.0
-        p = get_config(1).params().copy()
+        p = get_workload("ellipsoids_d7").params().copy()
         p[-1] = 0.7
         cases.append(Case(gpu_lib, sc.leaf_ijk, sc.depth, F, p, w.widths, 8))
         o_, d_ = random_rays(np.random.default_rng(seed), [1000, 257, 2049][i])

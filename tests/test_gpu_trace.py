@@ -7,7 +7,7 @@ import pytest
 
 from oracle.octree import Octree
 from oracle.trace import trace_hits as oracle_trace
-from synth.configs import get_config, tiny_workload
+from synth.configs import get_workload, tiny_workload
 from tests.helpers import crafted_occupancy, golden_case_arrays, load_golden, random_rays
 
 pytestmark = pytest.mark.gpu
@@ -76,24 +76,24 @@ def test_tiny_ellipsoid_scenes(gpu_lib, seed):
 
 
 def test_workload0_full_view(gpu_lib):
-    w = get_config(0)
+    w = get_workload("shell_d4")
     sc = w.scene()
     o, d = w.view_rays()
     exp = oracle_trace(Octree(sc.leaf_ijk, sc.depth), o, d, w.K)
-    _assert_identical(_gpu_trace(gpu_lib, sc.leaf_ijk, sc.depth, o, d, w.K), exp, "cfg0")
+    _assert_identical(_gpu_trace(gpu_lib, sc.leaf_ijk, sc.depth, o, d, w.K), exp, "shell_d4")
 
 
 def test_workload1_full_view_sampled(gpu_lib):
     """800x800 view traced on the GPU; a seeded sample of 4096 rays (plus the
     last ray) compared against the oracle."""
-    w = get_config(1)
+    w = get_workload("ellipsoids_d7")
     sc = w.scene()
     o, d = w.view_rays()
     got = _gpu_trace(gpu_lib, sc.leaf_ijk, sc.depth, o, d, w.K)
     rng = np.random.default_rng(123)
     idx = np.concatenate([rng.choice(o.shape[0], 4096, replace=False), [o.shape[0] - 1]])
     exp = oracle_trace(Octree(sc.leaf_ijk, sc.depth), o[idx], d[idx], w.K)
-    _assert_identical(tuple(a[idx] for a in got), exp, "cfg1 sample")
+    _assert_identical(tuple(a[idx] for a in got), exp, "ellipsoids_d7 sample")
     # whole-view invariants
     leaf, tin, tout, cnt = got
     assert cnt.max() <= w.K and (cnt > 0).mean() > 0.02

@@ -22,7 +22,7 @@ from oracle.render import (loss as oracle_loss, render as oracle_render, render_
                            render_backward_hit_magnitude,
                            render_backward_weight_scale)
 from oracle.trace import trace_hits as oracle_trace
-from synth.configs import get_config, get_multi
+from synth.configs import get_workload, get_multi
 from tests.gpu_cases import (C_PARAM, assert_bf16_render_close, assert_grad_close, assert_outputs_close,
                              decoder_kinks, psnr,
                              loss_scales, residual_terms)
@@ -36,9 +36,9 @@ def _t(x):
 
 
 @pytest.fixture(scope="module")
-def cfg2(gpu_lib):
+def ell_train(gpu_lib):
     import torch
-    w = get_config(2)
+    w = get_workload("ellipsoids_d7_train")
     sc = w.scene()
     F, p = w.features(), w.params()
     ob, db, rgb_t, dep_t = w.train_batch(w.batch, step=0)
@@ -65,7 +65,7 @@ def _train_step(gpu_lib, c, precision, params=None, lam=0.1):
     return gF, gp, out_rgb, out_dep, loss
 
 
-def test_cfg2_train_step_whole_batch_fp32(gpu_lib, cfg2):
+def test_ellipsoids_d7_train_step_whole_batch_fp32(gpu_lib, ell_train):
     """The FP32 train step on the whole 2^18-ray batch against the oracle's
     loss, outputs and gradients.  Rays at a kink of the loss (a decoder ReLU
     input or the L1 residual within rounding of zero) are part of the batch;
@@ -73,20 +73,20 @@ def test_cfg2_train_step_whole_batch_fp32(gpu_lib, cfg2):
     comparison (there FP32 and FP64 may take different one-sided
     derivatives), and their share of every decoder-parameter sum is far below
     the per-entry bound."""
-    w = cfg2["w"]
-    ob, db, rgb_t, dep_t = cfg2["batch"]
+    w = ell_train["w"]
+    ob, db, rgb_t, dep_t = ell_train["batch"]
     n = ob.shape[0]
     assert n == 1 << 18
-    gF, gp, r, dd, loss = _train_step(gpu_lib, cfg2, "fp32")
-    hits = oracle_trace(cfg2["oc"], ob, db, w.K)
-    er, ed, _, st = oracle_render(cfg2["oc"], cfg2["F"], cfg2["p"], w.widths, ob, db, hits)
+    gF, gp, r, dd, loss = _train_step(gpu_lib, ell_train, "fp32")
+    hits = oracle_trace(ell_train["oc"], ob, db, w.K)
+    er, ed, _, st = oracle_render(ell_train["oc"], ell_train["F"], ell_train["p"], w.widths, ob, db, hits)
     L, g_rgb, g_dep = oracle_loss(er, ed, rgb_t, dep_t, 0.1)
     eF, ep = render_backward(st, g_rgb, g_dep)
     mF, mp, mW = loss_scales(render_backward_hit_magnitude, render_backward_weight_scale, st, g_rgb,
                              residual_terms(g_rgb, er, rgb_t), g_dep)
     assert abs(float(loss.item()) - L) <= 1e-5 * abs(L)
-    assert_outputs_close(r.cpu().numpy(), er, 1.0, "cfg2 rgb")
-    assert_outputs_close(dd.cpu().numpy(), ed, max(1.0, np.abs(ed).max()), "cfg2 depth")
+    assert_outputs_close(r.cpu().numpy(), er, 1.0, "ell_train rgb")
+    assert_outputs_close(dd.cpu().numpy(), ed, max(1.0, np.abs(ed).max()), "ell_train depth")
     # a decoder kink changes the backward of its own hit only; the L1 kink
     # (depth residual at zero) that of every hit of the ray
     res = ed - dep_t
@@ -94,17 +94,17 @@ def test_cfg2_train_step_whole_batch_fp32(gpu_lib, cfg2):
     hit_k = decoder_kinks(st) | l1_kink[st.ray_i]
     masked = np.unique(st.corners[hit_k].ravel())
     reached = np.unique(st.corners.ravel())
-    print(f"cfg2: {st.ray_i.size} hits, {int(hit_k.sum())} at a kink, "
+    print(f"ell_train: {st.ray_i.size} hits, {int(hit_k.sum())} at a kink, "
           f"{masked.size} of {reached.size} feature rows left out")
     assert masked.size <= 0.2 * reached.size
     rows = np.ones(eF.shape[0], bool)
     rows[masked] = False
     g = gF.cpu().numpy()
-    assert_grad_close(g[rows], eF[rows], "cfg2 grad_features", mag=mF[rows], wmag=mW[rows])
-    assert_grad_close(gp.cpu().numpy(), ep, "cfg2 grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+    assert_grad_close(g[rows], eF[rows], "ell_train grad_features", mag=mF[rows], wmag=mW[rows])
+    assert_grad_close(gp.cpu().numpy(), ep, "ell_train grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
 
 
-def test_cfg2_directional_derivatives_of_gpu_loss(gpu_lib, cfg2):
+def test_ellipsoids_d7_train_directional_derivatives_of_gpu_loss(gpu_lib, ell_train):
     """Central differences along the GPU gradient direction (features, then
     decoder parameters) of the loss of the GPU's own FP32 render of the whole
     batch equal the directional derivative |g| that the GPU gradient
@@ -115,22 +115,22 @@ def test_cfg2_directional_derivatives_of_gpu_loss(gpu_lib, cfg2):
     a kink at every ray whose depth is near its target, which a finite step
     would cross; its gradient is checked against the oracle elsewhere)."""
     import torch
-    w = cfg2["w"]
-    ob, db, rgb_t, dep_t = cfg2["batch"]
+    w = ell_train["w"]
+    ob, db, rgb_t, dep_t = ell_train["batch"]
     n = ob.shape[0]
     opts = gpu_lib.make_opts(w.K, "voxel", "fp32")
     to, td = _t(ob), _t(db)
 
     def host_loss(params):
-        rgb, _, _ = gpu_lib.render([cfg2["scene"]], [n], params, w.widths, opts, to, td)
+        rgb, _, _ = gpu_lib.render([ell_train["scene"]], [n], params, w.widths, opts, to, td)
         torch.cuda.synchronize()
         r = rgb.cpu().numpy().astype(np.float64) - rgb_t
         return float(np.sum(r * r)) / (3.0 * n)
 
-    gF, gp, _, _, _ = _train_step(gpu_lib, cfg2, "fp32", lam=0.0)
-    L0 = host_loss(cfg2["params"])
-    F0 = cfg2["scene"].features.clone()
-    p0 = cfg2["params"].clone()
+    gF, gp, _, _, _ = _train_step(gpu_lib, ell_train, "fp32", lam=0.0)
+    L0 = host_loss(ell_train["params"])
+    F0 = ell_train["scene"].features.clone()
+    p0 = ell_train["params"].clone()
     for name, g in (("features", gF), ("params", gp)):
         gn = float(g.double().norm())
         assert gn > 0
@@ -139,13 +139,13 @@ def test_cfg2_directional_derivatives_of_gpu_loss(gpu_lib, cfg2):
         vals = []
         for sgn in (1.0, -1.0):
             if name == "features":
-                cfg2["scene"].features.copy_(F0 + sgn * eps * v)
+                ell_train["scene"].features.copy_(F0 + sgn * eps * v)
                 vals.append(host_loss(p0))
             else:
                 vals.append(host_loss(p0 + sgn * eps * v))
-        cfg2["scene"].features.copy_(F0)
+        ell_train["scene"].features.copy_(F0)
         fd = (vals[0] - vals[1]) / (2 * eps)
-        print(f"cfg2 {name}: directional derivative {fd:.6g}, |g| = {gn:.6g}")
+        print(f"ell_train {name}: directional derivative {fd:.6g}, |g| = {gn:.6g}")
         assert abs(fd - gn) <= 1e-2 * gn, (name, fd, gn)
 
 
@@ -310,7 +310,7 @@ def test_bf16_training_within_0p1_db_of_fp32(gpu_lib):
     the trajectory by about 0.1 dB from run to run."""
     import torch
     from paper_2205_07058_amd.train import Trainer
-    w = get_config(2)
+    w = get_workload("ellipsoids_d7_train")
     sc = w.scene()
     steps, bsz = 300, 1 << 15
     batches = [tuple(_t(x) for x in w.train_batch(bsz, step=1000 + it)) for it in range(steps)]

@@ -7,12 +7,12 @@ import pytest
 from oracle.octree import Octree
 from synth import scenes
 from synth.cameras import Camera
-from synth.configs import get_config, get_multi, tiny_workload
+from synth.configs import get_workload, get_multi, tiny_workload
 from synth.targets import render_targets
 
 
 def test_workload0_shell_sizes():
-    sc = get_config(0).scene()
+    sc = get_workload("shell_d4").scene()
     # exact min/max-distance shell test on the 16^3 grid
     assert sc.leaf_ijk.shape[0] == 712
     assert sc.n_vertices == 1194
@@ -20,7 +20,7 @@ def test_workload0_shell_sizes():
 
 
 def test_workload1_occupancy_about_three_percent():
-    sc = get_config(1).scene()
+    sc = get_workload("ellipsoids_d7").scene()
     assert 0.025 < sc.fraction < 0.04
     assert sc.n_vertices == Octree(sc.leaf_ijk, 7).n_vertices
 
