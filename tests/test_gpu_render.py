@@ -556,3 +556,20 @@ def test_full_items_of_max_hits(gpu_lib):
     mW = render_backward_weight_scale(st2, g_rgb, g_dep)
     assert_grad_close(gF, eF, "full items grad_features", mag=mF, wmag=mW)
     assert_grad_close(gp, ep, "full items grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+    # the deterministic reduction reads each hit's slot from the same map
+    import torch
+    to, td = case.rays(o[keep], d[keep])
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    det = []
+    for _ in range(2):
+        gFd = torch.zeros(case.scene.features.shape, dtype=torch.float32, device="cuda")
+        gpd = torch.zeros(case.params.shape, dtype=torch.float32, device="cuda")
+        opts = gpu_lib.make_opts(case.K, case.tau_mode, "fp32", gpu_lib.FLAG_DETERMINISTIC)
+        gpu_lib.render_backward([case.scene], [keep.size], case.params, case.widths, opts, to, td,
+                                t(g_rgb), t(g_dep), None, [gFd], gpd)
+        torch.cuda.synchronize()
+        det.append((gFd.cpu().numpy(), gpd.cpu().numpy()))
+    assert np.array_equal(det[0][0].view(np.int32), det[1][0].view(np.int32))
+    assert np.array_equal(det[0][1].view(np.int32), det[1][1].view(np.int32))
+    assert_grad_close(det[0][0], eF, "full items deterministic grad_features", mag=mF, wmag=mW)
+    assert_grad_close(det[0][1], ep, "full items deterministic grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
