@@ -183,6 +183,41 @@ def assert_bf16_render_close(rgb, dep, acc, ref, st, F, name=""):
     print(f"{name}: BF16 render max err / bound = {worst:.3g}")
 
 
+def lf_surface_point_error(st, F, grad_rgb, grad_depth):
+    """Per entry of the Z_C block of the light-field feature gradient, an
+    absolute bound on the error that the surface point's FP32 evaluation
+    carries into it.  eta = sigmoid(o_T1) inherits the FP32 error of the
+    density decoder's output (each layer's dot products off by gamma_n
+    sum |terms| plus |W| times the error of their inputs, the inputs'
+    interpolation off by 16 ulps of sum_j (w_j + D_j) |F_j|, r by 64 ulps);
+    x_s = eta x1 + (1 - eta) x2 then moves by |d eta| |x1 - x2| per axis and
+    each corner weight by sum_a |dw_j / du_a| |du_a|.  Where the density
+    decoder's activations are large this exceeds the few ulps of a cell
+    coordinate that the weight-sensitivity term assumes.  (C_C columns.)"""
+    from oracle.lightfield import _lf_backward_per_hit, weight_derivatives
+    ct = st.dec[0]
+    FT = np.abs(np.asarray(F, np.float64)[st.corners][:, :, :ct])
+    D1 = np.sum(np.abs(weight_derivatives(st.u1)), axis=2)
+    D2 = np.sum(np.abs(weight_derivatives(st.u2)), axis=2)
+    e = np.concatenate([16 * EPS32 * np.einsum("mj,mjc->mc", st.w1 + D1, FT),
+                        16 * EPS32 * np.einsum("mj,mjc->mc", st.w2 + D2, FT),
+                        64 * EPS32 * np.abs(st.r)], axis=1)
+    for li, (W, b) in enumerate(st.lt):
+        a = np.abs(st.actsT[li])
+        absW = np.abs(W)
+        n = W.shape[1] + 1
+        gamma = 1.01 * n * EPS32 / (1.0 - n * EPS32)
+        dz = e @ absW.T + gamma * (a @ absW.T + np.abs(b))
+        e = dz
+    deta = 0.25 * dz[:, 1] + 4 * EPS32
+    dus = deta[:, None] * np.abs(st.x1 - st.x2) / st.h + 8 * EPS32
+    dwj = np.einsum("mja,ma->mj", np.abs(weight_derivatives(st.us)), dus)
+    _, _, _, _, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth)
+    E = np.zeros((st.n_vertices, g_zC.shape[1]))
+    np.add.at(E, st.corners.ravel(), (dwj[:, :, None] * np.abs(g_zC)[:, None, :]).reshape(-1, g_zC.shape[1]))
+    return E
+
+
 def _dense(v, st, fill):
     """Per-hit values (m, ...) into the dense per-ray layout (n, K, ...)."""
     v = np.asarray(v, np.float64)

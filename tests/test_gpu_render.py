@@ -8,8 +8,8 @@ from oracle.render import (bf16_round, loss as oracle_loss, mlp_forward as oracl
                            render_backward_hit_magnitude,
                            render_backward_weight_scale)
 from synth.configs import get_workload, scene_from_leaves, tiny_workload, xavier_params
-from tests.gpu_cases import (C_PARAM, C_W_LF, Case, assert_bf16_render_close, assert_grad_close, assert_outputs_close,
-                             bf16_decoder_bound, psnr,
+from tests.gpu_cases import (C_PARAM, C_W_LF, EPS32, Case, assert_bf16_render_close, assert_grad_close,
+                             assert_outputs_close, bf16_decoder_bound, lf_surface_point_error, psnr,
                              loss_scales, residual_terms)
 from tests.helpers import random_rays
 
@@ -573,3 +573,56 @@ def test_full_items_of_max_hits(gpu_lib):
     assert np.array_equal(det[0][1].view(np.int32), det[1][1].view(np.int32))
     assert_grad_close(det[0][0], eF, "full items deterministic grad_features", mag=mF, wmag=mW)
     assert_grad_close(det[0][1], ep, "full items deterministic grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
+
+
+def test_full_items_of_max_hits_light_field(gpu_lib):
+    """The light-field kernels on the same fully occupied depth-5 scene: every
+    ray keeps K = 16 hits, so the backward kernels' item-wide hit maps are
+    full (4,096 hits per item).  Forward on every ray and gradients on the
+    rays clear of decoder kinks against the oracle."""
+    from tests.gpu_cases import LfCase
+    from tests.helpers import crafted_occupancy
+    from oracle.lightfield import render_lf_backward, render_lf_backward_hit_magnitude, render_lf_backward_weight_scale
+    from oracle.lightfield import widths_of
+    from oracle.render import split_params
+    leaves = crafted_occupancy("full", 5).astype(np.int32)
+    rng = np.random.default_rng(78)
+    F = rng.normal(0, 0.5, (33 ** 3, 96)).astype(np.float32)
+    # hidden biases of 0.5 keep most ReLU inputs clear of zero, so that most
+    # rays (16 hits each) are free of decoder kinks and the gradient rays
+    # still fill whole work items
+    wt, wc = widths_of(tuple(gpu_lib.LF_DECODERS), False)
+    nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
+    p = LfCase.random(gpu_lib, 17, 5, K=16).p.astype(np.float64)
+    for _, b in split_params(p[:nt], wt)[:-1] + split_params(p[nt:], wc)[:-1]:
+        b[:] = 0.5
+    lf = LfCase(gpu_lib, leaves, 5, F, p.astype(np.float32), 16)
+    n = 2 * 256 + 37
+    v = rng.standard_normal((n, 3))
+    o = (3.0 * v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    d = rng.uniform(-0.2, 0.2, (n, 3)) - o
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    lr, ld, la, lst = lf.oracle(o, d)
+    assert np.all(np.bincount(lst.ray_i, minlength=n) == 16)
+    lrgb, ldep, lacc = lf.gpu_render(o, d)
+    assert_outputs_close(lrgb, lr, 1.0, "full items lf rgb")
+    assert_outputs_close(ldep, ld, max(1.0, np.abs(ld).max()), "full items lf depth")
+    keep = lf.smooth_rays(o, d)
+    assert keep.size > 256                  # at least one full work item of kink-free rays
+    g_rgb = rng.normal(size=(keep.size, 3)).astype(np.float32)
+    g_dep = rng.normal(size=keep.size).astype(np.float32)
+    gF, gp = lf.gpu_backward(o[keep], d[keep], g_rgb, g_dep)
+    _, _, _, st2 = lf.oracle(o[keep], d[keep])
+    eF, ep = render_lf_backward(st2, g_rgb, g_dep)
+    mF, mp = render_lf_backward_hit_magnitude(st2, g_rgb, g_dep)
+    mW = render_lf_backward_weight_scale(st2, g_rgb, g_dep)
+    ct = lf.dec[0]
+    assert_grad_close(gF[:, :ct], eF[:, :ct], "full items lf grad Z_T", mag=mF[:, :ct], wmag=mW[:, :ct],
+                      c_w=C_W_LF)
+    # Z_C: the hidden biases make the density decoder's activations large,
+    # and eta's FP32 error moves the surface point by more than the few ulps
+    # the weight-sensitivity term assumes; its own bound is added
+    E = lf_surface_point_error(st2, lf.F, g_rgb, g_dep)
+    assert_grad_close(gF[:, ct:], eF[:, ct:], "full items lf grad Z_C", mag=mF[:, ct:],
+                      wmag=mW[:, ct:] + 2.0 * E / (C_W_LF * EPS32), c_w=C_W_LF)
+    assert_grad_close(gp, ep, "full items lf grad_params", rel_nw=1e-4, mag=mp, c=C_PARAM)
