@@ -184,9 +184,12 @@ def assert_bf16_render_close(rgb, dep, acc, ref, st, F, name=""):
 
 
 def lf_surface_point_error(st, F, grad_rgb, grad_depth):
-    """Per entry of the Z_C block of the light-field feature gradient, an
-    absolute bound on the error that the surface point's FP32 evaluation
-    carries into it.  eta = sigmoid(o_T1) inherits the FP32 error of the
+    """Per entry of the Z_C block of the light-field feature gradient, the
+    error that the surface point's FP32 evaluation carries into it through
+    the corner weights (a moved x_s also changes dL/dpsi(x_s) through the
+    colour decoder; that part is relative to the entry's own contributions
+    and the caller's factor 2 is meant for it, a measured margin rather than
+    a derived one).  eta = sigmoid(o_T1) inherits the FP32 error of the
     density decoder's output (each layer's dot products off by gamma_n
     sum |terms| plus |W| times the error of their inputs, the inputs'
     interpolation off by 16 ulps of sum_j (w_j + D_j) |F_j|, r by 64 ulps);
