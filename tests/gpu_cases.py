@@ -183,7 +183,7 @@ def assert_bf16_render_close(rgb, dep, acc, ref, st, F, name=""):
     print(f"{name}: BF16 render max err / bound = {worst:.3g}")
 
 
-def lf_surface_point_error(st, F, grad_rgb, grad_depth):
+def lf_surface_point_error(st, F, grad_rgb, grad_depth, deta=None):
     """Per entry of the Z_C block of the light-field feature gradient, the
     error that the surface point's FP32 evaluation carries into it through
     the corner weights (a moved x_s also changes dL/dpsi(x_s) through the
@@ -196,24 +196,28 @@ def lf_surface_point_error(st, F, grad_rgb, grad_depth):
     x_s = eta x1 + (1 - eta) x2 then moves by |d eta| |x1 - x2| per axis and
     each corner weight by sum_a |dw_j / du_a| |du_a|.  Where the density
     decoder's activations are large this exceeds the few ulps of a cell
-    coordinate that the weight-sensitivity term assumes.  (C_C columns.)"""
+    coordinate that the weight-sensitivity term assumes.  (C_C columns.)
+    ``deta`` (per hit) replaces the derived bound on eta's error."""
     from oracle.lightfield import _lf_backward_per_hit, weight_derivatives
     ct = st.dec[0]
-    FT = np.abs(np.asarray(F, np.float64)[st.corners][:, :, :ct])
-    D1 = np.sum(np.abs(weight_derivatives(st.u1)), axis=2)
-    D2 = np.sum(np.abs(weight_derivatives(st.u2)), axis=2)
-    e = np.concatenate([16 * EPS32 * np.einsum("mj,mjc->mc", st.w1 + D1, FT),
-                        16 * EPS32 * np.einsum("mj,mjc->mc", st.w2 + D2, FT),
-                        64 * EPS32 * np.abs(st.r)], axis=1)
-    for li, (W, b) in enumerate(st.lt):
-        a = np.abs(st.actsT[li])
-        absW = np.abs(W)
-        n = W.shape[1] + 1
-        gamma = 1.01 * n * EPS32 / (1.0 - n * EPS32)
-        dz = e @ absW.T + gamma * (a @ absW.T + np.abs(b))
-        e = dz
-    deta = 0.25 * dz[:, 1] + 4 * EPS32
-    dus = deta[:, None] * np.abs(st.x1 - st.x2) / st.h + 8 * EPS32
+    if deta is None:
+        FT = np.abs(np.asarray(F, np.float64)[st.corners][:, :, :ct])
+        D1 = np.sum(np.abs(weight_derivatives(st.u1)), axis=2)
+        D2 = np.sum(np.abs(weight_derivatives(st.u2)), axis=2)
+        e = np.concatenate([16 * EPS32 * np.einsum("mj,mjc->mc", st.w1 + D1, FT),
+                            16 * EPS32 * np.einsum("mj,mjc->mc", st.w2 + D2, FT),
+                            64 * EPS32 * np.abs(st.r)], axis=1)
+        for li, (W, b) in enumerate(st.lt):
+            a = np.abs(st.actsT[li])
+            absW = np.abs(W)
+            n = W.shape[1] + 1
+            gamma = 1.01 * n * EPS32 / (1.0 - n * EPS32)
+            dz = e @ absW.T + gamma * (a @ absW.T + np.abs(b))
+            e = dz
+        deta = 0.25 * dz[:, 1] + 4 * EPS32
+        dus = deta[:, None] * np.abs(st.x1 - st.x2) / st.h + 8 * EPS32
+    else:
+        dus = np.asarray(deta, np.float64)[:, None] * np.abs(st.x1 - st.x2) / st.h
     dwj = np.einsum("mja,ma->mj", np.abs(weight_derivatives(st.us)), dus)
     _, _, _, _, g_zC = _lf_backward_per_hit(st, grad_rgb, grad_depth)
     E = np.zeros((st.n_vertices, g_zC.shape[1]))

@@ -622,3 +622,35 @@ def test_stage_loss_gradients_against_central_differences(kind):
         g = (Lp - Lm) / (2 * eps)
         assert abs(g - gp[k]) <= 1e-6 * abs(g) + floor(eps), (k, g, gp[k])
     assert skipped <= 0.1 * (checked + skipped)
+
+
+def test_surface_point_error_scale_bounds_the_corner_weight_change():
+    """The test helper's surface-point scale, given eta's change, bounds the
+    change of every Z_C entry that the moved corner weights cause (with
+    dL/dpsi(x_s) held fixed): eta moved through the density decoder's o_T1
+    bias by delta, |d eta| = eta (1 - eta) delta to first order."""
+    from oracle.lightfield import _lf_backward_per_hit
+    from tests.gpu_cases import lf_surface_point_error
+    for seed in (5, 6, 7):
+        oc, F, p, dec, o, d, hits, _, _ = _fd_case(seed, "direct")
+        _, _, _, st = render_lf(oc, F, p, dec, o, d, hits)
+        rng = np.random.default_rng(9)
+        g_rgb = rng.normal(size=(o.shape[0], 3))
+        g_dep = rng.normal(size=o.shape[0])
+        _, _, _, _, g_zC = _lf_backward_per_hit(st, g_rgb, g_dep)
+        wt, _ = widths_of(dec)
+        nt = sum(a * b + b for a, b in zip(wt[:-1], wt[1:]))
+        delta = 1e-6
+        p2 = p.copy()
+        p2[nt - 1] += delta                       # bias of o_T1
+        _, _, _, st2 = render_lf(oc, F, p2, dec, o, d, hits)
+        dW = st2.ws - st.ws
+        actual = np.zeros((st.n_vertices, g_zC.shape[1]))
+        np.add.at(actual, st.corners.ravel(), (dW[:, :, None] * g_zC[:, None, :]).reshape(-1, g_zC.shape[1]))
+        E = lf_surface_point_error(st, F, g_rgb, g_dep, deta=st.eta * (1.0 - st.eta) * delta)
+        assert np.abs(actual).max() > 0
+        assert np.all(np.abs(actual) <= E * (1 + 1e-4) + 1e-18), seed
+        # tight where one hit dominates an entry (a scale too large by a
+        # constant factor fails here)
+        big = np.abs(actual) > 0.5 * np.abs(actual).max()
+        assert np.min(E[big] / np.abs(actual[big])) < 1.1, seed
