@@ -30,13 +30,18 @@ Tolerances (FP32 path, derived from the arithmetic):
   entry's own contributions, so a small or cancelling entry is checked at its
   own scale.  Gradient parity uses rays with no decoder pre-activation within
   1e-4 of a ReLU kink (there FP32 and FP64 may legitimately take different
-  one-sided derivatives).
+  one-sided derivatives).  On rays with many hits Eq. 3's dL/dtau is a small
+  difference of large terms; tests of such rays take M at the conditioning
+  of each hit's dL/dX (render_backward_hit_magnitude(conditioned=True)), and
+  where large density-decoder activations make eta's FP32 error move the
+  light field's surface point by more than a few ulps, the Z_C entries add
+  that error's own scale (lf_surface_point_error).
 BF16 path: compared with the oracle's BF16-rounding mode; hidden activations
 may round differently where FP32 and FP64 accumulations straddle a bfloat16
-rounding boundary (one bfloat16 ulp = 2^-8 relative), so rendered outputs are
-checked at max|err| <= 2^-6 max|ref| + 1e-4 S, and the error against the FP64
-oracle is reported as PSNR; single-decoder renders are also checked per ray
-(bf16_render_bound).  The decoder alone is checked per entry
+rounding boundary (one bfloat16 ulp = 2^-8 relative).  Single-decoder renders
+are checked per ray (bf16_render_bound), light-field renders at
+max|err| <= 2^-6 max|ref| + 1e-4 S, and the error against the FP64 oracle is
+reported as PSNR.  The decoder alone is checked per entry
 (bf16_decoder_bound): each output within the error that FP32 accumulation
 can produce, carried through the layers, where a hidden activation may take
 the neighbouring bfloat16 value only if its exact pre-activation lies within
